@@ -1,0 +1,189 @@
+/*
+ * atabu.h -- C ABI of the MI355X (gfx950) Tabu-search scheduler for
+ * base-returning air-ambulance routes (Tassone & Choudhury, "Algorithms for
+ * Optimizing Fleet Scheduling of Air Ambulances", arXiv 2002.11710).
+ *
+ * Problem (Section 3 of the paper): M missions, each a pickup location and a
+ * delivery location, are to be flown by V vehicles; every vehicle starts and
+ * ends at its own base and flies its missions in order, going from one
+ * mission's delivery to the next mission's pickup.  The objective (Eq (2)) is
+ * the total flight time, each mission's loaded leg included.  Times come from
+ * the haversine distance over the vehicle speed (Eq (1)).
+ *
+ * Method (Section 4): a greedy start (Algorithm 1), then neighbourhood search
+ * (Algorithm 2) or Tabu search (Algorithm 3).  Here every iteration scores every
+ * relocate move (a mission to any gap of any route, Figure 2) and every swap of
+ * two missions, masks moves that put a mission back into a vehicle it left
+ * less than `tenure` iterations ago unless they beat the best objective found,
+ * picks the smallest (delta, move index) and applies it.  All iterations of a
+ * solve run inside one kernel launch.
+ *
+ * Conventions for every function below:
+ *   - Return 0 (AT_OK) on success, a negative AT_E* code otherwise; the text of
+ *     the last error of the calling thread is at_last_error().
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example torch CUDA tensors); "host" pointers are ordinary memory.  The
+ *     caller owns every buffer; the library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that return
+ *     host scalars synchronise that stream before they return.
+ *   - Integers are int32 unless stated; objectives are int64 seconds.
+ *   - Inputs are checked before any search kernel runs; a bad input returns an
+ *     error and leaves outputs untouched.
+ */
+#ifndef ATABU_H
+#define ATABU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AT_OK 0
+#define AT_EINVAL (-1)   /* bad size, index, pickup == delivery, bad parameter */
+#define AT_ERANGE (-2)   /* a travel time outside [0, 2^27), or too many move slots */
+#define AT_ENOMEM (-3)   /* workspace too small, or a request over the memory budget */
+#define AT_EAGAIN (-4)   /* result not ready yet (serving) */
+#define AT_EDEVICE (-5)  /* a HIP error or a device-side failure */
+
+#define AT_TABU 0        /* Tabu search (Algorithm 3) */
+#define AT_NS 1          /* neighbourhood search (Algorithm 2): stops at a local optimum */
+
+/* Schedules (at_params.schedule). */
+#define AT_SCHED_AUTO 0
+#define AT_SCHED_WG 1    /* one workgroup per solve, the whole state in LDS */
+#define AT_SCHED_MULTI 2 /* several workgroups per solve, state replicated in each one's LDS */
+#define AT_SCHED_GLOBAL 3 /* several workgroups per solve, state in HBM (large instances) */
+
+/* One instance.  Locations are numbered 0..n_locs-1; the travel matrix gives
+ * integer seconds, travel[i*n_locs + j] = time from location i to location j
+ * (for example the output of at_build_travel).  Mission m is flown from
+ * pickup[m] to delivery[m]; vehicle v starts and ends at vehicle_loc[v].
+ * Limits: 1 <= n_locs <= 65535, 0 <= n_missions <= 65535, 1 <= n_vehicles
+ * <= 65535, pickup != delivery, every travel time in [0, 2^27), and
+ * M*(M+V) + M*(M-1)/2 < 2^32. */
+typedef struct at_instance {
+    int32_t n_locs;
+    const int32_t *travel;       /* device, n_locs*n_locs, row-major */
+    int32_t n_missions;
+    const int32_t *pickup;       /* device, n_missions */
+    const int32_t *delivery;     /* device, n_missions */
+    int32_t n_vehicles;
+    const int32_t *vehicle_loc;  /* device, n_vehicles */
+} at_instance;
+
+typedef struct at_params {
+    int32_t variant;        /* AT_TABU or AT_NS */
+    int32_t tenure;         /* >= 0: iterations a mission may not re-enter the vehicle it left */
+    int32_t max_iters;      /* >= 0 */
+    int32_t aspiration;     /* 1: a tabu move is allowed when it beats the best objective */
+    uint64_t restart_seed;  /* 0: greedy start in mission order; else a SplitMix64-driven
+                               Fisher-Yates order of the missions */
+    int32_t trace;          /* 1: write the per-iteration trace into at_result */
+    int32_t schedule;       /* AT_SCHED_* (AUTO picks by size) */
+    int32_t n_groups;       /* workgroups per solve for MULTI/GLOBAL (0 = auto) */
+    int32_t block;          /* threads per workgroup: 0 = auto, else 256, 512 or 1024 */
+    int32_t chunk;          /* columns per work unit: 0 = auto, else 8, 16, 32 or 64 */
+    int32_t reserved;
+} at_params;
+
+/* Results of one solve.  Arrays are device memory supplied by the caller;
+ * scalars are written by the library (host).  The routes are the best
+ * solution seen (the greedy start counts, best_iter = -1).  Route v holds
+ * missions route_seq[route_off[v] .. route_off[v+1]) in flying order;
+ * route_of[m] is the vehicle of mission m.  Trace record t (t < iters_done):
+ * the slot index of the applied move (0xFFFFFFFF when no move exists), its
+ * delta, the objective after it, and flags: bit0 swap move, bit1 the move was
+ * tabu but allowed by aspiration, bit2 every allowed move was tabu and the best
+ * tabu move was taken.  Slot indices: relocating mission m into gap G is
+ * m*(M+V) + G, where the gaps of vehicle v are numbered G = (missions on
+ * vehicles before v) + v + g, g = 0..(missions on v), gap g lying before the
+ * g-th mission of the route (g = missions on v: before the return to base);
+ * swapping missions a < b is M*(M+V) + a*M - a*(a+1)/2 + (b - a - 1). */
+typedef struct at_result {
+    int32_t *route_off;     /* device, V+1 */
+    int32_t *route_seq;     /* device, M */
+    int32_t *route_of;      /* device, M (may be NULL) */
+    uint32_t *tr_move;      /* device, max_iters (NULL when trace == 0) */
+    int32_t *tr_delta;      /* device, max_iters */
+    int64_t *tr_obj;        /* device, max_iters */
+    uint8_t *tr_flags;      /* device, max_iters */
+    int64_t best_obj;       /* out */
+    int64_t final_obj;      /* out: objective after the last iteration */
+    int32_t iters_done;     /* out: iterations run (NS: moves applied) */
+    int32_t best_iter;      /* out */
+    int32_t status;         /* out: AT_OK or the solve's error code */
+    int32_t reserved;
+} at_result;
+
+/* Eq (1): travel-time matrix of n points.  lat_deg, lon_deg: device, n
+ * doubles (degrees); travel: device, n*n int32 written row-major with
+ * round-half-away-from-zero of 2*6371*asin(sqrt(min(1, a))) * 3600 / speed,
+ * a = sin^2(dlat/2) + cos(lat_i) cos(lat_j) sin^2(dlon/2), in FP64 without
+ * contraction.  Asynchronous on `stream`.  AT_EINVAL if n < 1, n > 65535 or
+ * speed <= 0. */
+int at_build_travel(int32_t n, const double *lat_deg, const double *lon_deg, double speed_kmh,
+                    int32_t *travel, void *stream);
+
+/* Bytes of device workspace at_solve_batch needs for these instances and
+ * parameters (n_inst entries each, n_restarts solves per instance).  0 on bad
+ * arguments. */
+size_t at_workspace_size(int32_t n_inst, const at_instance *insts, const at_params *params,
+                         int32_t n_restarts);
+
+/* Solve one instance: greedy start, then the search (Sections 4.1-4.3).
+ * ws: device workspace of ws_bytes >= at_workspace_size(1, inst, params, 1).
+ * Blocking on `stream`; fills out's device arrays and host scalars. */
+int at_solve(const at_instance *inst, const at_params *params, void *ws, size_t ws_bytes,
+             void *stream, at_result *out);
+
+/* Solve n_inst instances x n_restarts restarts.  params[i] applies to
+ * instance i; restart r of instance i starts from restart_seed 0 when r == 0
+ * and from params[i].restart_seed + r otherwise.  out has n_inst*n_restarts
+ * entries, solve (i, r) at out[i*n_restarts + r].  Every solve gives the same
+ * result as the corresponding at_solve.  Blocking on `stream`. */
+int at_solve_batch(int32_t n_inst, const at_instance *insts, const at_params *params,
+                   int32_t n_restarts, void *ws, size_t ws_bytes, void *stream,
+                   at_result *out);
+
+/* Test hook: the 64-bit key of every move slot for a given state, as the
+ * search kernels compute them (bit63 tabu-and-not-aspirated, bits 62..32
+ * delta + 2^30, bits 31..0 slot index; UINT64_MAX for a slot that is not a
+ * move).  route_off (V+1), route_seq (M), tabu_until (M*V, entry m*V+v = last
+ * iteration at which mission m may not enter vehicle v, -1 = never) and
+ * keys_out (M*(M+V) + M*(M-1)/2) are device pointers.  t is the iteration,
+ * cur and best the current and best objectives.  Blocking. */
+int at_debug_eval_moves(const at_instance *inst, const at_params *params,
+                        const int32_t *route_off, const int32_t *route_seq,
+                        const int32_t *tabu_until, int32_t t, int64_t cur, int64_t best,
+                        uint64_t *keys_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Serving with continuous batching.  A server owns device memory up to
+ * hbm_budget_bytes and up to max_slots concurrent solves.  Submitted requests
+ * wait until a slot and enough budget are free, then join the solves already
+ * on the GPU: the device advances every resident solve `chunk_iters`
+ * iterations per launch, so requests that arrive while others run start
+ * within one chunk.  Each request's result is the same as at_solve's.
+ * at_server_submit copies what it needs from the instance (device arrays are
+ * read on the server's stream before it returns) and returns a ticket;
+ * at_server_poll returns AT_OK with the result when done (out's arrays are
+ * device memory of the caller, filled then), AT_EAGAIN while pending;
+ * at_server_progress drives the device (call it from one thread, in a loop);
+ * at_server_destroy waits for running work and frees everything. */
+int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_iters,
+                     void *stream, void **server);
+int at_server_submit(void *server, const at_instance *inst, const at_params *params,
+                     uint64_t *ticket);
+int at_server_progress(void *server, int32_t *n_active);
+int at_server_poll(void *server, uint64_t ticket, at_result *out);
+int at_server_destroy(void *server);
+
+/* Thread-local text of the last error returned on this thread. */
+const char *at_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATABU_H */

@@ -1,0 +1,180 @@
+// atabu_internal.h -- data layouts shared by the library's kernels and its host
+// code (never by the oracle).
+//
+// Device representation of an instance (built once per instance by the
+// prepare kernel):
+//   * The search only ever needs a flight from some location a vehicle LEAVES
+//     (a mission's delivery or a base) to some location it ENTERS (a mission's
+//     pickup or a base).  The prepare kernel therefore renumbers the exit
+//     locations 0..R-1 and the entry locations 0..C-1 in increasing location
+//     order and stores the R x C block of the travel matrix, row stride Cs,
+//     as uint16 when every travel time fits (else int32).  Mission m keeps
+//     mrow[m] = (exit row of its delivery) * Cs and mcol[m] = entry column of
+//     its pickup; vehicle v keeps vrow[v], vcol[v] for its base.  Each
+//     mission's loaded leg (pickup -> delivery) is the same in every solution,
+//     so only their sum svc_sum is kept.
+//   * The stride Cs makes rows land on different LDS banks: Cs = 2 mod 4 for
+//     16-bit entries (odd in dwords), odd for 32-bit entries.
+//
+// Solve state (per solve, in LDS for the LDS-resident schedules):
+//   seq[i]   mission at flat position i (routes concatenated by vehicle)
+//   off[v]   first flat position of vehicle v, off[V] = M
+//   rt[i]    vehicle of flat position i
+//   pof[m], rof[m]  flat position / vehicle of mission m
+//   tabu[v*M + m] = 1 + last iteration at which m may not enter v (0 = never)
+// Per-iteration arrays (rebuilt from the state every iteration):
+//   per position i: xr = exit row offset of the predecessor (or base),
+//                   yc = entry column of the successor (or base),
+//                   outv = T[xr][p_m] + T[d_m][yc], link = T[xr][yc]
+//   per gap G (G = i + rt[i] is the gap before position i, G = off[v+1] + v
+//   the gap before vehicle v's return): ga = exit row offset on its left,
+//   gb = entry column on its right, gc = T[ga][gb], gr = its vehicle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace at {
+
+constexpr int kWave = 64;
+constexpr uint64_t kKeyNone = ~0ull;
+constexpr int32_t kDeltaBias = 1 << 30;
+constexpr int32_t kMaxTravel = 1 << 27;       // travel times must be below this
+constexpr int kMaxLocs = 65535;
+constexpr int kMaxMissions = 65535;
+constexpr int kMaxVehicles = 65535;
+
+struct InstDev {
+    // filled by the host
+    int32_t L, M, V;
+    int32_t pad0;
+    const int32_t *T, *p, *d, *b;     // caller's device arrays
+    int32_t *exit_loc, *enter_loc;    // workspace, L each
+    int32_t *mrow, *mcol, *vrow, *vcol;
+    void *tc;                         // workspace, capacity tc_cap bytes
+    int64_t tc_cap;
+    // filled by the prepare kernel
+    int32_t status;
+    int32_t R, C, Cs, esz;            // esz = 2 or 4 bytes per compact entry
+    int32_t maxT;
+    int64_t svc_sum;
+};
+
+struct JobScal {
+    int64_t best_obj, final_obj;
+    int32_t iters_done, best_iter, status, stopped;
+};
+
+// Saved search state (for chunked execution and the HBM-resident schedule).
+struct SolveState {
+    int32_t *seq, *off, *tabu;        // M, V+1, M*V (tabu in the 1 + until encoding)
+    int64_t cur, best;
+    int32_t t, best_iter, stopped, valid;
+};
+
+struct JobDev {
+    const InstDev *inst;
+    int32_t variant, tenure, max_iters, aspiration, trace;
+    int32_t t_begin, t_end;           // iterations run by this launch
+    int32_t resume, save;             // load / store `st`
+    int32_t tb16;                     // tabu entries stored as uint16 in LDS
+    int32_t chunk;                    // columns per work unit
+    int32_t pad1;
+    uint64_t seed;
+    int32_t *out_off, *out_seq, *out_of;
+    uint32_t *tr_move;
+    int32_t *tr_delta;
+    int64_t *tr_obj;
+    uint8_t *tr_flags;
+    JobScal *scal;
+    SolveState *st;
+};
+
+// Cross-workgroup exchange for the multi-workgroup schedules.
+struct Xchg {
+    uint64_t key[3];
+    uint32_t cnt;
+    uint32_t abort;
+    uint32_t queue;
+    uint32_t pad[3];
+};
+
+struct Lay {
+    uint32_t tc, mrow, mcol, vrow, vcol, off, seq, rt, rof, pof;
+    uint32_t xr, yc, outv, link, ga, gb, gc, gr, tabu, red, total;
+};
+
+__host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
+
+__host__ __device__ inline Lay lds_layout(int M, int V, int R, int Cs, int esz, int tbsz)
+{
+    Lay l;
+    uint32_t o = 0;
+    uint32_t uM = (uint32_t)M, uV = (uint32_t)V, NG = uM + uV;
+#define AT_TAKE(field, bytes) do { l.field = o; o = al16(o + (uint32_t)(bytes)); } while (0)
+    AT_TAKE(tc, (uint64_t)R * (uint64_t)Cs * (uint64_t)esz);
+    AT_TAKE(mrow, 4 * uM);
+    AT_TAKE(mcol, 4 * uM);
+    AT_TAKE(vrow, 4 * uV);
+    AT_TAKE(vcol, 4 * uV);
+    AT_TAKE(off, 4 * (uV + 1));
+    AT_TAKE(seq, 2 * uM);
+    AT_TAKE(rt, 2 * uM);
+    AT_TAKE(rof, 2 * uM);
+    AT_TAKE(pof, 2 * uM);
+    AT_TAKE(xr, 4 * uM);
+    AT_TAKE(yc, 4 * uM);
+    AT_TAKE(outv, 4 * NG);      // also greedy scratch (needs max(M, V))
+    AT_TAKE(link, 4 * NG);
+    AT_TAKE(ga, 4 * NG);
+    AT_TAKE(gb, 4 * NG);
+    AT_TAKE(gc, 4 * NG);
+    AT_TAKE(gr, 2 * NG);
+    AT_TAKE(tabu, (uint64_t)tbsz * uM * uV);
+    AT_TAKE(red, 512);
+#undef AT_TAKE
+    l.total = o;
+    return l;
+}
+
+// Compact-matrix stride for C entry columns of esz bytes.
+__host__ __device__ inline int compact_stride(int C, int esz)
+{
+    if (C < 1) C = 1;
+    if (esz == 2) {
+        int s = C;
+        while ((s & 3) != 2) ++s;
+        return s;
+    }
+    return C | 1;
+}
+
+// Upper bound of the exit rows / entry columns of an instance.
+__host__ __device__ inline int64_t compact_bound(int L, int M, int V)
+{
+    int64_t r = (int64_t)M + V;
+    return r < L ? r : L;
+}
+
+inline int64_t n_slots(int64_t M, int64_t V) { return M * (M + V) + M * (M - 1) / 2; }
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_travel(int32_t n, const double *lat, const double *lon, double speed,
+                         int32_t *out, hipStream_t s);
+hipError_t launch_prepare(InstDev *insts, int32_t n, hipStream_t s);
+hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, Xchg *xs, int grid, int block,
+                            uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
+hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
+                               uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
+hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_t *seq,
+                             const int32_t *tabu_until, int32_t t, int64_t cur, int64_t best,
+                             uint64_t *keys, int block, uint32_t lds_bytes, int esz16,
+                             hipStream_t s);
+int max_groups_multi(int block, uint32_t lds_bytes, int tb16, int esz16);
+uint32_t max_lds_bytes();
+int num_cus();
+hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+
+}  // namespace at

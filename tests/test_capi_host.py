@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/atabu.h declares, and rejects bad scalar arguments
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+at = pytest.importorskip("paper_2002_11710_amd")
+from paper_2002_11710_amd import _capi  # noqa: E402
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "atabu.h")).read()
+    return sorted(set(re.findall(r"\b(at_[a-z_]+)\s*\(", src)))
+
+
+def test_header_functions_are_exported():
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    L = _capi.lib()
+    names = _declared()
+    assert "at_solve" in names and "at_build_travel" in names and len(names) >= 11
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _fake_inst(L=10, M=3, V=2):
+    return _capi._Instance(L, 0x1000, M, 0x2000, 0x3000, V, 0x4000)
+
+
+@pytest.mark.parametrize("mut,code", [
+    (dict(n_locs=0), _capi.AT_EINVAL),
+    (dict(n_locs=70000), _capi.AT_EINVAL),
+    (dict(n_missions=-1), _capi.AT_EINVAL),
+    (dict(n_vehicles=0), _capi.AT_EINVAL),
+    (dict(travel=None), _capi.AT_EINVAL),
+    (dict(n_missions=65535, n_vehicles=65535), _capi.AT_ERANGE),
+])
+def test_bad_instance_scalars(mut, code):
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    inst = _fake_inst()
+    for k, v in mut.items():
+        setattr(inst, k, v)
+    pr = _capi.make_params()
+    res = _capi._Result()
+    res.route_off = 0x5000
+    res.route_seq = 0x6000
+    rc = _capi.lib().at_solve(C.byref(inst), C.byref(pr), C.c_void_p(0x7000), 1 << 20, None,
+                              C.byref(res))
+    assert rc == code
+    assert _capi.lib().at_last_error()
+
+
+@pytest.mark.parametrize("mut", [dict(variant=3), dict(tenure=-1), dict(max_iters=-2),
+                                 dict(block=100), dict(chunk=5), dict(schedule=9),
+                                 dict(n_groups=-1)])
+def test_bad_params(mut):
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    inst = _fake_inst()
+    pr = _capi.make_params()
+    for k, v in mut.items():
+        setattr(pr, k, v)
+    res = _capi._Result()
+    res.route_off = 0x5000
+    res.route_seq = 0x6000
+    rc = _capi.lib().at_solve(C.byref(inst), C.byref(pr), C.c_void_p(0x7000), 1 << 20, None,
+                              C.byref(res))
+    assert rc == _capi.AT_EINVAL
+    assert _capi.lib().at_workspace_size(1, C.byref(inst), C.byref(pr), 1) == 0
+
+
+def test_workspace_too_small_and_build_travel_args():
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    inst = _fake_inst()
+    pr = _capi.make_params()
+    need = _capi.lib().at_workspace_size(1, C.byref(inst), C.byref(pr), 1)
+    assert need > 0
+    res = _capi._Result()
+    res.route_off = 0x5000
+    res.route_seq = 0x6000
+    rc = _capi.lib().at_solve(C.byref(inst), C.byref(pr), C.c_void_p(0x7000), need - 1, None,
+                              C.byref(res))
+    assert rc == _capi.AT_ENOMEM
+    L = _capi.lib()
+    assert L.at_build_travel(0, 0x1, 0x2, 260.0, 0x3, None) == _capi.AT_EINVAL
+    assert L.at_build_travel(5, 0x1, 0x2, -1.0, 0x3, None) == _capi.AT_EINVAL
+    assert L.at_build_travel(5, None, 0x2, 260.0, 0x3, None) == _capi.AT_EINVAL

@@ -1,0 +1,200 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, bit for bit.
+
+Everything here is integer work (travel seconds, deltas, keys, objectives,
+whole trajectories), so the bar is exact equality.  Inputs are the seeded
+synthetic workloads of gen.instances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gen.instances import (batch_instance, batch_specs, brute_twin, m400_instance, make_instance,
+                           restart_seed, small_instance, stress_instance)
+from helpers import assert_same_result, oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+at = pytest.importorskip("paper_2002_11710_amd")
+
+
+def _dev(inst):
+    return at.DeviceInstance.from_instance(inst)
+
+
+# ------------------------------------------------------------------ Eq (1)
+
+@pytest.mark.parametrize("maker", [small_instance, brute_twin, m400_instance, stress_instance])
+def test_travel_matrix_bit_exact(maker):
+    inst = maker(0)
+    T = at.build_travel(inst.lat, inst.lon).cpu().numpy()
+    assert np.array_equal(T, oracle.travel(inst.lat, inst.lon))
+
+
+def test_travel_matrix_batch_sample():
+    for spec in batch_specs(64)[::8]:
+        inst = batch_instance(spec)
+        T = at.build_travel(inst.lat, inst.lon).cpu().numpy()
+        assert np.array_equal(T, oracle.travel(inst.lat, inst.lon)), spec["index"]
+
+
+# ------------------------------------------------------------------ keys of every slot
+
+def _random_state(P, rng, tenure_span=6):
+    M, V = P.M, P.V
+    perm = rng.permutation(M).astype(np.int32)
+    cuts = np.sort(rng.integers(0, M + 1, size=V - 1))
+    off = np.concatenate([[0], cuts, [M]]).astype(np.int32)
+    tabu = np.where(rng.random((M, V)) < 0.3, rng.integers(5, 5 + tenure_span, (M, V)), -1)
+    return off, perm, tabu.astype(np.int32)
+
+
+@pytest.mark.parametrize("shape", [(20, 2, 1, 1), (20, 2, 1, 2), (20, 3, 3, 12), (30, 2, 5, 70),
+                                   (60, 4, 7, 130), (120, 10, 16, 400)])
+@pytest.mark.parametrize("chunk", [8, 32])
+def test_every_slot_key(shape, chunk):
+    F, B, V, M = shape
+    inst = make_instance(7 + M, F, B, V, M)
+    P = oracle.Problem.from_instance(inst)
+    dev = _dev(inst)
+    rng = np.random.default_rng(M * 31 + V)
+    states = [(*P.greedy(0), np.full((M, V), -1, np.int32))]
+    for _ in range(3):
+        states.append(_random_state(P, rng))
+    for k, (off, seq, tabu) in enumerate(states):
+        cur = P.objective(off, seq)
+        for best in (cur, cur - 50):
+            for t in (0, 6, 9):
+                want = P.keys(off, seq, tabu, t, cur, best)
+                got = at.debug_eval_moves(dev, off, seq, tabu, t, cur, best, chunk=chunk)
+                bad = np.nonzero(got != want)[0]
+                assert bad.size == 0, (shape, k, t, best - cur, bad[:5], got[bad[:5]], want[bad[:5]])
+
+
+# ------------------------------------------------------------------ whole trajectories
+
+def test_small_workload_tabu_trajectory():
+    inst = small_instance(0)
+    P, o = oracle_solve(inst)
+    g = at.solve(_dev(inst), tenure=inst.tenure, iters=inst.iters)
+    assert_same_result(o, g, "3x12 tabu")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_workload_seeds_and_ns(seed):
+    inst = small_instance(seed)
+    _, o = oracle_solve(inst, restart_seed=seed * 977)
+    g = at.solve(_dev(inst), tenure=7, iters=500, restart_seed=seed * 977)
+    assert_same_result(o, g, f"3x12 seed {seed}")
+    _, o = oracle_solve(inst, variant=oracle.NS, iters=500)
+    g = at.solve(_dev(inst), variant=at.AT_NS, iters=500)
+    assert_same_result(o, g, f"3x12 NS seed {seed}")
+
+
+def test_brute_twin_reaches_optimum_on_gpu():
+    inst = brute_twin(0)
+    _, o = oracle_solve(inst)
+    g = at.solve(_dev(inst), tenure=7, iters=500)
+    assert_same_result(o, g, "2x6")
+    assert g["best_obj"] == 105168   # brute-force optimum of this instance (tests/test_oracle_search.py)
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 8), (2, 0)])
+def test_m400_tabu_trajectory(sched, groups):
+    inst = m400_instance(0)
+    _, o = _m400_oracle(0)
+    g = at.solve(_dev(inst), tenure=15, iters=5000, schedule=sched, n_groups=groups)
+    assert_same_result(o, g, f"16x400 tabu sched {sched}/{groups}")
+
+
+def test_m400_ns_trajectory():
+    inst = m400_instance(0)
+    _, o = _m400_oracle(1)
+    for sched in (1, 2):
+        g = at.solve(_dev(inst), variant=at.AT_NS, tenure=15, iters=5000, schedule=sched)
+        assert_same_result(o, g, f"16x400 NS sched {sched}")
+
+
+_M400 = {}
+
+
+def _m400_oracle(variant):
+    if variant not in _M400:
+        _M400[variant] = oracle_solve(m400_instance(0), variant=variant, tenure=15, iters=5000)
+    return _M400[variant]
+
+
+def test_batch_matches_oracle_and_solo():
+    specs = batch_specs(24)[::3]          # 8 uneven instances
+    insts = [batch_instance(s) for s in specs]
+    for s, inst in zip(specs, insts):
+        inst.iters = 300
+    devs = [_dev(i) for i in insts]
+    params = [at._capi.make_params(at.AT_TABU, s["tenure"], 300, True, s["seed"], True)
+              for s in specs]
+    res = at.solve_batch(devs, params, n_restarts=2)
+    for i, (s, inst) in enumerate(zip(specs, insts)):
+        for r in range(2):
+            _, o = oracle_solve(inst, tenure=s["tenure"], iters=300,
+                                restart_seed=restart_seed(s["seed"], r))
+            assert_same_result(o, res[i * 2 + r], f"batch {i} restart {r}")
+
+
+def test_edge_cases():
+    # no missions
+    inst = make_instance(3, 10, 2, 3, 0)
+    _, o = oracle_solve(inst, iters=5)
+    g = at.solve(_dev(inst), tenure=3, iters=5)
+    assert g["best_obj"] == 0 and g["iters_done"] == 5
+    assert np.all(g["tr_move"].cpu().numpy().view(np.uint32) == 0xFFFFFFFF)
+    # one mission, one vehicle: no move exists
+    inst = make_instance(4, 10, 1, 1, 1)
+    _, o = oracle_solve(inst, iters=4)
+    g = at.solve(_dev(inst), tenure=3, iters=4)
+    assert_same_result(o, g, "1x1")
+    # one vehicle, ragged tile (M = 65)
+    inst = make_instance(5, 40, 1, 1, 65)
+    _, o = oracle_solve(inst, tenure=5, iters=60)
+    g = at.solve(_dev(inst), tenure=5, iters=60)
+    assert_same_result(o, g, "1x65")
+    # tenure 0 and aspiration off
+    inst = make_instance(6, 30, 3, 5, 40)
+    _, o = oracle_solve(inst, tenure=0, iters=100)
+    g = at.solve(_dev(inst), tenure=0, iters=100)
+    assert_same_result(o, g, "tenure 0")
+    _, o = oracle_solve(inst, tenure=9, iters=100, aspiration=0)
+    g = at.solve(_dev(inst), tenure=9, iters=100, aspiration=False)
+    assert_same_result(o, g, "no aspiration")
+
+
+def test_bad_device_inputs_are_rejected():
+    inst = small_instance(0)
+    dev = _dev(inst)
+    bad = at.DeviceInstance(dev.travel, dev.pickup, dev.pickup, dev.vehicle_loc)   # pickup == delivery
+    with pytest.raises(at.AtError) as e:
+        at.solve(bad, iters=3)
+    assert e.value.code == at.AT_EINVAL
+    T = dev.travel.clone()
+    T[1, 2] = -5
+    with pytest.raises(at.AtError) as e:
+        at.solve(at.DeviceInstance(T, dev.pickup, dev.delivery, dev.vehicle_loc), iters=3)
+    assert e.value.code == at.AT_ERANGE
+    import torch
+    p = dev.pickup.clone()
+    p[0] = 10 ** 6
+    with pytest.raises(at.AtError) as e:
+        at.solve(at.DeviceInstance(dev.travel, p, dev.delivery, dev.vehicle_loc), iters=3)
+    assert e.value.code == at.AT_EINVAL
+    assert torch.cuda.is_available()
+
+
+def test_determinism_repeated():
+    inst = make_instance(11, 60, 4, 6, 90)
+    dev = _dev(inst)
+    first = at.solve(dev, tenure=9, iters=400)
+    tm = first["tr_move"].cpu().numpy()
+    for block, chunk in ((256, 8), (512, 16), (1024, 64)):
+        g = at.solve(dev, tenure=9, iters=400, block=block, chunk=chunk, schedule=1)
+        assert np.array_equal(g["tr_move"].cpu().numpy(), tm), (block, chunk)
+    for groups in (2, 5):
+        g = at.solve(dev, tenure=9, iters=400, schedule=2, n_groups=groups)
+        assert np.array_equal(g["tr_move"].cpu().numpy(), tm), groups
