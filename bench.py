@@ -1,0 +1,278 @@
+"""Benchmark: Tabu-search move evaluations per second at M = 400.
+
+One step = the whole hot path on the 16-vehicle x 400-mission workload
+(10 bases, 120 facilities, seed 0): the travel matrix from the coordinates
+(Eq (1)), then a Tabu search of 5000 iterations with tenure 15 and a
+neighbourhood search on the same instance, each a greedy start plus every
+iteration's relocate + swap evaluation, tabu mask, argmin and apply, all in
+the HIP library.  Inputs (coordinates, missions, vehicle bases) are resident
+in HBM before timing starts.
+
+value = valid moves scored per second over the whole step (245 400 per
+iteration), whole GPU.  Also reported: Tabu iterations per second, the search
+kernel's roofline (integer VALU work per launch over its HIP-event duration),
+optionally the uneven-batch solves per second (--batch), and the oracle timed
+on the host as the CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch N] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# int32 VALU lane-operations per clock per CU (4 SIMDs x 16 lanes) x 256 CUs x 2.4 GHz
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# algorithmic integer work per scored move: relocate = 2 address adds + 3 delta adds
+# + 1 min-select; swap = 4 address adds + 5 delta adds + 1 min-select
+OPS_RELOCATE, OPS_SWAP = 6, 10
+# algorithmic LDS bytes per scored move (a 16-bit gather counted as one 4-byte bank access):
+# relocate 2 travel gathers + 1 tabu read, swap 4 gathers + 2 tabu reads
+LDS_RELOCATE, LDS_SWAP = 12, 24
+
+
+def move_counts(M: int, V: int):
+    """(valid relocates, swaps) scored per iteration."""
+    return M * (M + V - 2), M * (M - 1) // 2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also time an uneven batch of this many instances x 8 restarts")
+    ap.add_argument("--serve", type=str, default="",
+                    help="also run the serving stream at these arrival rates (req/s, comma separated)")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--groups", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(inst, budget_s=20.0):
+    """The oracle (plain C, single thread) on the same workload, bounded sample."""
+    import oracle
+    P = oracle.Problem.from_instance(inst)
+    rel, swp = move_counts(P.M, P.V)
+    t0 = time.perf_counter()
+    iters = 0
+    # Tabu in slices until the budget is used (the full run is 5000 iterations)
+    n = 500
+    r = P.solve(variant=0, tenure=15, iters=n, trace=False)
+    iters += n
+    dt = time.perf_counter() - t0
+    while dt < budget_s * 0.5 and iters < 5000:
+        n2 = min(5000, 2 * n)
+        t1 = time.perf_counter()
+        P.solve(variant=0, tenure=15, iters=n2, trace=False)
+        dt = time.perf_counter() - t1
+        iters, n = n2, n2
+    evals = iters * (rel + swp)
+    return dict(value=evals / dt, unit="move evals/s", cores=1, kind="oracle",
+                sample=f"oracle Tabu search on the 16x400 workload, {iters} iterations "
+                       f"(single thread, {dt:.2f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(a single instance shares one device; see the sharding notes in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import m400_instance
+
+    torch.cuda.set_device(0)
+    inst = m400_instance(0)
+    M, V, ITERS, TEN = inst.n_missions, inst.n_vehicles, 5000, 15
+    lat = torch.tensor(inst.lat, dtype=torch.float64, device="cuda")
+    lon = torch.tensor(inst.lon, dtype=torch.float64, device="cuda")
+    travel = torch.empty((inst.n_locs, inst.n_locs), dtype=torch.int32, device="cuda")
+    dev = at.DeviceInstance(travel, inst.pickup, inst.delivery, inst.vehicle_loc)
+    L = at.lib()
+    stream = torch.cuda.current_stream()
+
+    import ctypes as C
+    pr_tabu = at._capi.make_params(at.AT_TABU, TEN, ITERS, True, 0, True, args.schedule,
+                                   args.groups)
+    pr_ns = at._capi.make_params(at.AT_NS, TEN, ITERS, True, 0, True, args.schedule, args.groups)
+    ci = dev.c_struct()
+    nbytes = int(L.at_workspace_size(1, C.byref(ci), C.byref(pr_tabu), 1))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out_t = at._capi._alloc_result(M, V, ITERS, True, "cuda")
+    out_n = at._capi._alloc_result(M, V, ITERS, True, "cuda")
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def step():
+        at._capi._check(L.at_build_travel(inst.n_locs, C.c_void_p(lat.data_ptr()),
+                                          C.c_void_p(lon.data_ptr()), 260.0,
+                                          C.c_void_p(travel.data_ptr()), sp))
+        rt = at._capi._c_result(out_t)
+        at._capi._check(L.at_solve(C.byref(ci), C.byref(pr_tabu), C.c_void_p(ws.data_ptr()),
+                                   nbytes, sp, C.byref(rt)))
+        rn = at._capi._c_result(out_n)
+        at._capi._check(L.at_solve(C.byref(ci), C.byref(pr_ns), C.c_void_p(ws.data_ptr()),
+                                   nbytes, sp, C.byref(rn)))
+        return rt, rn
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    tabu_ms, ns_ms, ns_iters = [], [], []
+    for _ in range(args.steps):
+        rt, rn = step()
+        tabu_ms.append(rt.search_ms)
+        ns_ms.append(rn.search_ms)
+        ns_iters.append(rn.iters_done)
+        assert rt.status == 0 and rn.status == 0
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1000.0 / args.steps
+    rel, swp = move_counts(M, V)
+    per_iter = rel + swp
+    evals_per_step = per_iter * (ITERS + float(np.mean(ns_iters)))
+    value = evals_per_step / (ms_per_step / 1000.0)
+    tabu_launch_ms = float(np.mean(tabu_ms))
+    ops = ITERS * (rel * OPS_RELOCATE + swp * OPS_SWAP)
+    achieved = ops / (tabu_launch_ms / 1000.0)
+    lds_bytes = ITERS * (rel * LDS_RELOCATE + swp * LDS_SWAP)
+    line = {
+        "metric": "move evals/s (M=400 Tabu + NS step)",
+        "value": value,
+        "unit": "move evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "16 vehicles x 400 missions, 10 bases, 120 facilities, seed 0; "
+                               "Tabu 5000 iterations tenure 15 + neighbourhood search",
+                   "moves_per_iter": per_iter, "iters": ITERS},
+        "tabu_iters_per_s": ITERS / (tabu_launch_ms / 1000.0),
+        "tabu_search_ms": tabu_launch_ms,
+        "ns_search_ms": float(np.mean(ns_ms)),
+        "ns_iters": float(np.mean(ns_iters)),
+        "best_obj": int(rt.best_obj),
+        "event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                     "kernel": "k_search (Tabu launch)",
+                     "lds_GBps": lds_bytes / (tabu_launch_ms / 1000.0) / 1e9},
+    }
+    if args.batch:
+        line["batch"] = bench_batch(args.batch)
+    if args.serve:
+        line["serving"] = [bench_serve(float(x), args.serve_requests) for x in args.serve.split(",")]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(inst)
+    print(json.dumps(line))
+
+
+def bench_batch(n_inst: int, restarts: int = 8):
+    """Uneven batch: n_inst instances x restarts restarts, 2000 iterations each, one call."""
+    import numpy as np
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import batch_instance, batch_specs
+
+    specs = batch_specs(n_inst)
+    insts = [batch_instance(s) for s in specs]
+    devs = [at.DeviceInstance.from_instance(i) for i in insts]
+    params = [at._capi.make_params(at.AT_TABU, s["tenure"], s["iters"], True, s["seed"], False)
+              for s in specs]
+    outs = []
+    for i in insts:
+        for _ in range(restarts):
+            outs.append(at._capi._alloc_result(i.n_missions, i.n_vehicles, 2000, False, "cuda"))
+    ws = None
+    res = at.solve_batch(devs, params, restarts, outs=outs)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = at.solve_batch(devs, params, restarts, outs=outs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evals = 0
+    ops = 0
+    for s in specs:
+        rel, swp = move_counts(s["n_missions"], s["n_vehicles"])
+        evals += restarts * 2000 * (rel + swp)
+        ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
+    kms = float(res[0]["search_ms"])
+    assert all(r["status"] == 0 for r in res)
+    return {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
+            "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
+            "move_evals_per_s": evals / wall, "search_ms": kms,
+            "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS}
+
+
+def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,
+                budget: int = 64 << 30):
+    """Open-loop Poisson stream of n_req requests at rate lam through the
+    continuous-batching server; latency = result on the host minus scheduled
+    arrival.  Instances are uploaded before the clock starts."""
+    import numpy as np
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import make_instance, poisson_arrivals, serve_specs
+
+    specs = serve_specs(n_req)
+    arrivals = poisson_arrivals(n_req, lam, stream_seed=2 + int(lam))
+    devs = [at.DeviceInstance.from_instance(make_instance(s["seed"], s["n_fac"], s["n_bases"],
+                                                          s["n_vehicles"], s["n_missions"]))
+            for s in specs]
+    torch.cuda.synchronize()
+    srv = at.Server(budget, max_slots=slots, chunk_iters=chunk)
+    done = {}
+    submitted = 0
+    tickets = {}
+    t0 = time.perf_counter()
+    while len(done) < n_req:
+        now = time.perf_counter() - t0
+        while submitted < n_req and arrivals[submitted] <= now:
+            s = specs[submitted]
+            tickets[srv.submit(devs[submitted], tenure=s["tenure"], iters=s["iters"],
+                               trace=False)] = submitted
+            submitted += 1
+        srv.progress()
+        for tk in list(tickets):
+            r = srv.poll(tk)
+            if r is not None:
+                k = tickets.pop(tk)
+                assert r["status"] == 0
+                done[k] = time.perf_counter() - t0
+        if not tickets and submitted < n_req:
+            time.sleep(max(0.0, min(0.001, arrivals[submitted] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([done[k] - arrivals[k] for k in range(n_req)]) * 1000.0
+    return {"lambda_req_per_s": lam, "requests": n_req, "wall_s": wall,
+            "solves_per_s": n_req / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "chunk_iters": chunk, "max_slots": slots}
+
+
+if __name__ == "__main__":
+    main()

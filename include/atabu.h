@@ -42,7 +42,7 @@ extern "C" {
 
 #define AT_OK 0
 #define AT_EINVAL (-1)   /* bad size, index, pickup == delivery, bad parameter */
-#define AT_ERANGE (-2)   /* a travel time outside [0, 2^27), or too many move slots */
+#define AT_ERANGE (-2)   /* a travel time outside [0, 2^23), or too many move slots */
 #define AT_ENOMEM (-3)   /* workspace too small, or a request over the memory budget */
 #define AT_EAGAIN (-4)   /* result not ready yet (serving) */
 #define AT_EDEVICE (-5)  /* a HIP error or a device-side failure */
@@ -61,7 +61,7 @@ extern "C" {
  * (for example the output of at_build_travel).  Mission m is flown from
  * pickup[m] to delivery[m]; vehicle v starts and ends at vehicle_loc[v].
  * Limits: 1 <= n_locs <= 65535, 0 <= n_missions <= 65535, 1 <= n_vehicles
- * <= 65535, pickup != delivery, every travel time in [0, 2^27), and
+ * <= 65535, pickup != delivery, every travel time in [0, 2^23), and
  * M*(M+V) + M*(M-1)/2 < 2^32. */
 typedef struct at_instance {
     int32_t n_locs;
@@ -114,7 +114,9 @@ typedef struct at_result {
     int32_t iters_done;     /* out: iterations run (NS: moves applied) */
     int32_t best_iter;      /* out */
     int32_t status;         /* out: AT_OK or the solve's error code */
-    int32_t reserved;
+    float search_ms;        /* out: duration of the search launch that ran this solve, in ms,
+                               from HIP events recorded on `stream` around it (a batch shares
+                               one launch per kernel class; every solve of it reports that) */
 } at_result;
 
 /* Eq (1): travel-time matrix of n points.  lat_deg, lon_deg: device, n
@@ -147,12 +149,13 @@ int at_solve_batch(int32_t n_inst, const at_instance *insts, const at_params *pa
                    int32_t n_restarts, void *ws, size_t ws_bytes, void *stream,
                    at_result *out);
 
-/* Test hook: the 64-bit key of every move slot for a given state, as the
- * search kernels compute them (bit63 tabu-and-not-aspirated, bits 62..32
- * delta + 2^30, bits 31..0 slot index; UINT64_MAX for a slot that is not a
- * move).  route_off (V+1), route_seq (M), tabu_until (M*V, entry m*V+v = last
- * iteration at which mission m may not enter vehicle v, -1 = never) and
- * keys_out (M*(M+V) + M*(M-1)/2) are device pointers.  t is the iteration,
+/* Test hook: the 64-bit key of every move slot for a given state, one move at
+ * a time (bit63 tabu-and-not-aspirated, bits 62..32 delta + 2^30, bits 31..0
+ * slot index; UINT64_MAX for a slot that is not a move), followed by the
+ * minimum key the search's own evaluation finds for that state.  route_off
+ * (V+1), route_seq (M), tabu_until (M*V, entry m*V+v = last iteration at which
+ * mission m may not enter vehicle v, -1 = never) and keys_out
+ * (M*(M+V) + M*(M-1)/2 + 1 entries) are device pointers.  t is the iteration,
  * cur and best the current and best objectives.  Blocking. */
 int at_debug_eval_moves(const at_instance *inst, const at_params *params,
                         const int32_t *route_off, const int32_t *route_seq,

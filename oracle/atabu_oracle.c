@@ -40,7 +40,9 @@
  * enumeration of every solution (and a Held-Karp subset DP) for the optimum
  * the search must not beat; or_delta_inc against or_delta_def on every move of
  * random solutions; route invariants after every step; the neighbourhood
- * search stopping only at a true local optimum.
+ * search stopping only at a true local optimum.  The exact trajectory of
+ * or_solve (which move each iteration takes) is parity unpinned beyond those
+ * properties: the paper prints no worked trajectory to check it against.
  */
 #define _GNU_SOURCE 1
 #include <math.h>
@@ -343,7 +345,7 @@ static int check_inst(const or_inst *in)
     for (int32_t v = 0; v < in->V; ++v)
         if (in->b[v] < 0 || in->b[v] >= in->L) return OR_EINVAL;
     for (int64_t k = 0; k < (int64_t)in->L * in->L; ++k)
-        if (in->T[k] < 0 || in->T[k] >= (1 << 27)) return OR_ERANGE;
+        if (in->T[k] < 0 || in->T[k] >= (1 << 23)) return OR_ERANGE;
     return OR_OK;
 }
 

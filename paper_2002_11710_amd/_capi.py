@@ -43,7 +43,7 @@ class _Result(C.Structure):
                 ("tr_move", C.c_void_p), ("tr_delta", C.c_void_p), ("tr_obj", C.c_void_p),
                 ("tr_flags", C.c_void_p), ("best_obj", C.c_int64), ("final_obj", C.c_int64),
                 ("iters_done", C.c_int32), ("best_iter", C.c_int32), ("status", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("search_ms", C.c_float)]
 
 
 _lib = None
@@ -57,6 +57,9 @@ def lib():
         if _lib is None:
             if not os.path.exists(lib_path):
                 raise AtError(AT_EDEVICE, f"{lib_path} is missing: run paper_2002_11710_amd/build.py")
+            # Load torch's HIP runtime first: the library then binds to the same
+            # runtime (same SONAME) instead of pulling a second one into the process.
+            import torch  # noqa: F401
             L = C.CDLL(lib_path)
             vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
             L.at_build_travel.argtypes = [i32, vp, vp, C.c_double, vp, vp]
@@ -178,7 +181,7 @@ def _c_result(bufs) -> _Result:
                    g("tr_move").data_ptr() if "tr_move" in bufs else None,
                    g("tr_delta").data_ptr() if "tr_delta" in bufs else None,
                    g("tr_obj").data_ptr() if "tr_obj" in bufs else None,
-                   g("tr_flags").data_ptr() if "tr_flags" in bufs else None, 0, 0, 0, 0, 0, 0)
+                   g("tr_flags").data_ptr() if "tr_flags" in bufs else None, 0, 0, 0, 0, 0, 0.0)
 
 
 def _finish(bufs, res: _Result, M: int):
@@ -190,7 +193,7 @@ def _finish(bufs, res: _Result, M: int):
         if name in bufs:
             out[name] = bufs[name][:k]
     out.update(best_obj=res.best_obj, final_obj=res.final_obj, iters_done=res.iters_done,
-               best_iter=res.best_iter, status=res.status)
+               best_iter=res.best_iter, status=res.status, search_ms=res.search_ms)
     return out
 
 
@@ -265,11 +268,12 @@ def debug_eval_moves(inst: DeviceInstance, route_off, route_seq, tabu_until, t, 
     off = torch.as_tensor(np.asarray(route_off, dtype=np.int32)).to(dev)
     seq = torch.as_tensor(np.asarray(route_seq, dtype=np.int32)).to(dev)
     tab = torch.as_tensor(np.asarray(tabu_until, dtype=np.int32).reshape(-1)).to(dev)
-    keys = torch.full((max(n, 1),), -1, dtype=torch.int64, device=dev)
+    keys = torch.full((n + 1,), -1, dtype=torch.int64, device=dev)
     _check(lib().at_debug_eval_moves(C.byref(ci), C.byref(pr), _dptr(off), _dptr(seq), _dptr(tab),
                                      int(t), int(cur), int(best), _dptr(keys), _dptr(ws),
                                      ws.numel(), _stream_ptr(stream)))
-    return keys.cpu().numpy().view(np.uint64)[:n]
+    k = keys.cpu().numpy().view(np.uint64)
+    return k[:n], int(k[n])
 
 
 class Server:

@@ -1,10 +1,11 @@
-// api.hip -- host side of the C ABI declared in include/atabu.h.
+// api.hip -- host side of the C ABI declared in include/atabu.h (solve, batch,
+// travel matrix, key dump).  The serving calls live in server.hip and share
+// the engine functions declared in engine.h.
 //
 // Every call validates its scalar arguments on the host, copies a small
 // descriptor table into the caller's device workspace, runs the prepare kernel
 // (device-side checks of the instance arrays and the compact travel block),
-// reads back the per-instance status, then launches the search.  Nothing is
-// allocated except by the server (at_server_*), which owns its memory.
+// reads back the per-instance status, picks a schedule per solve and launches.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -15,6 +16,7 @@
 
 #include "atabu.h"
 #include "atabu_internal.h"
+#include "engine.h"
 
 namespace at {
 
@@ -36,9 +38,8 @@ int hip_fail(hipError_t e, const char *what)
     return fail(AT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+const char *last_error() { return g_err.c_str(); }
 
-// Host-side check of one instance's scalars and one parameter set.
 int check_scalars(const at_instance *in, const at_params *pr)
 {
     if (!in || !pr) return fail(AT_EINVAL, "null instance or params");
@@ -62,88 +63,119 @@ int check_scalars(const at_instance *in, const at_params *pr)
     if (pr->chunk != 0 && (pr->chunk != 8 && pr->chunk != 16 && pr->chunk != 32 && pr->chunk != 64))
         return fail(AT_EINVAL, "chunk must be 0, 8, 16, 32 or 64");
     if (pr->schedule < AT_SCHED_AUTO || pr->schedule > AT_SCHED_GLOBAL) return fail(AT_EINVAL, "bad schedule");
-    if (pr->n_groups < 0) return fail(AT_EINVAL, "negative n_groups");
+    if (pr->n_groups < 0 || pr->n_groups > 4096) return fail(AT_EINVAL, "n_groups outside [0, 4096]");
     return AT_OK;
 }
 
 // ---------------------------------------------------------------------------
-// workspace carving
+// sizes
 // ---------------------------------------------------------------------------
-struct InstPlan {
-    size_t exit_loc, enter_loc, mrow, mcol, vrow, vcol, tc;
-    int64_t tc_cap;
-};
-
-struct WsPlan {
-    size_t xchg, insts, jobs, scal, states, end;
-    std::vector<InstPlan> ip;
-    std::vector<size_t> st_arrays;   // per job: base of seq|off|tabu
-};
-
-static int64_t tc_capacity(const at_instance &in)
+static int64_t tc_capacity(int L, int M, int V)
 {
-    const int64_t B = compact_bound(in.n_locs, in.n_missions, in.n_vehicles);
+    const int64_t B = compact_bound(L, M, V);
     return B * (B + 4) * 4;
 }
 
-static WsPlan plan_ws(int32_t n_inst, const at_instance *insts, int32_t n_jobs, bool with_state)
+int tabu_bytes(const at_params &pr) { return ((int64_t)pr.max_iters + pr.tenure + 1 <= 65535) ? 2 : 4; }
+
+bool may_need_global(const at_instance &in, const at_params &pr)
+{
+    if (pr.schedule == AT_SCHED_GLOBAL) return true;
+    const int64_t B = compact_bound(in.n_locs, in.n_missions, in.n_vehicles);
+    const uint32_t worst = lds_layout(in.n_missions, in.n_vehicles, (int)B, compact_stride((int)B, 4), 4,
+                                      tabu_bytes(pr)).total;
+    return worst > kLdsLimit;
+}
+
+size_t inst_bytes(const at_instance &in)
+{
+    size_t o = 0;
+    o += al256(4 * (size_t)in.n_locs) * 2;
+    o += al256(4 * (size_t)in.n_missions) * 2;
+    o += al256(4 * (size_t)in.n_vehicles) * 2;
+    o += al256((size_t)tc_capacity(in.n_locs, in.n_missions, in.n_vehicles));
+    return o;
+}
+
+size_t gstate_bytes(const at_instance &in, const at_params &pr)
+{
+    return al256(sizeof(GlobalBufs)) + al256(global_state_bytes(in.n_missions, in.n_vehicles, tabu_bytes(pr)));
+}
+
+void carve_inst(InstDev &d, const at_instance &in, char *base)
+{
+    size_t o = 0;
+    d.L = in.n_locs; d.M = in.n_missions; d.V = in.n_vehicles;
+    d.T = in.travel; d.p = in.pickup; d.d = in.delivery; d.b = in.vehicle_loc;
+    d.exit_loc = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_locs);
+    d.enter_loc = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_locs);
+    d.mrow = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_missions);
+    d.mcol = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_missions);
+    d.vrow = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_vehicles);
+    d.vcol = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_vehicles);
+    d.tc = (void *)(base + o);
+    d.tc_cap = tc_capacity(in.n_locs, in.n_missions, in.n_vehicles);
+    d.status = AT_EDEVICE;
+}
+
+void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
+{
+    (void)tbsz;
+    auto a = [](uint64_t x) { return (size_t)((x + 255u) & ~(uint64_t)255u); };
+    const uint64_t uM = (uint64_t)M, uV = (uint64_t)V;
+    size_t o = al256(sizeof(GlobalBufs));
+    for (int k = 0; k < 2; ++k) {
+        g.seq[k] = (uint16_t *)(base + o); o += a(2 * uM);
+        g.rt[k] = (uint16_t *)(base + o); o += a(2 * uM);
+        g.pof[k] = (uint16_t *)(base + o); o += a(2 * uM);
+        g.rof[k] = (uint16_t *)(base + o); o += a(2 * uM);
+        g.off[k] = (int32_t *)(base + o); o += a(4 * (uV + 1));
+    }
+    g.posA = (int4 *)(base + o); o += a(16 * uM);
+    g.posB = (int4 *)(base + o); o += a(16 * uM);
+    g.gap = (int4 *)(base + o); o += a(16 * (uM + uV));
+    g.prank = (uint8_t *)(base + o); o += a(uM);
+    g.tabu = (void *)(base + o);
+    g.cur = 0;
+    g.pad = 0;
+}
+
+struct WsPlan {
+    size_t xchg, insts, jobs, scal, states, end;
+    std::vector<size_t> inst_off;
+    std::vector<size_t> gstate_off;   // per job, 0 = none reserved
+};
+
+static WsPlan plan_ws(int32_t n_inst, const at_instance *insts, const at_params *params,
+                      int32_t n_restarts)
 {
     WsPlan p;
+    const int32_t n_jobs = n_inst * n_restarts;
     size_t o = 0;
     p.xchg = o; o = al256(o + sizeof(Xchg));
     p.insts = o; o = al256(o + sizeof(InstDev) * (size_t)n_inst);
-    p.ip.resize((size_t)n_inst);
-    for (int32_t i = 0; i < n_inst; ++i) {
-        const at_instance &in = insts[i];
-        InstPlan &q = p.ip[(size_t)i];
-        q.exit_loc = o; o = al256(o + 4 * (size_t)in.n_locs);
-        q.enter_loc = o; o = al256(o + 4 * (size_t)in.n_locs);
-        q.mrow = o; o = al256(o + 4 * (size_t)in.n_missions);
-        q.mcol = o; o = al256(o + 4 * (size_t)in.n_missions);
-        q.vrow = o; o = al256(o + 4 * (size_t)in.n_vehicles);
-        q.vcol = o; o = al256(o + 4 * (size_t)in.n_vehicles);
-        q.tc_cap = tc_capacity(in);
-        q.tc = o; o = al256(o + (size_t)q.tc_cap);
-    }
+    p.inst_off.resize((size_t)n_inst);
+    for (int32_t i = 0; i < n_inst; ++i) { p.inst_off[(size_t)i] = o; o += inst_bytes(insts[i]); }
     p.jobs = o; o = al256(o + sizeof(JobDev) * (size_t)n_jobs);
     p.scal = o; o = al256(o + sizeof(JobScal) * (size_t)n_jobs);
-    p.states = o;
-    if (with_state) o = al256(o + sizeof(SolveState) * (size_t)n_jobs);
-    p.st_arrays.assign((size_t)n_jobs, 0);
+    p.states = o; o = al256(o + sizeof(SolveState) * (size_t)n_jobs);
+    p.gstate_off.assign((size_t)n_jobs, 0);
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const int32_t i = k / n_restarts;
+        if (may_need_global(insts[i], params[i])) {
+            p.gstate_off[(size_t)k] = o;
+            o += gstate_bytes(insts[i], params[i]);
+        }
+    }
     p.end = o;
     return p;
-}
-
-static size_t state_bytes(const at_instance &in)
-{
-    const size_t M = (size_t)in.n_missions, V = (size_t)in.n_vehicles;
-    return al256(4 * M) + al256(4 * (V + 1)) + al256(4 * M * V);
 }
 
 // ---------------------------------------------------------------------------
 // prepare: upload descriptors, run the checks, read back per-instance results
 // ---------------------------------------------------------------------------
-static int prepare(int32_t n_inst, const at_instance *insts, char *ws, const WsPlan &p,
-                   hipStream_t s, std::vector<InstDev> &host)
+int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s)
 {
-    host.assign((size_t)n_inst, InstDev{});
-    for (int32_t i = 0; i < n_inst; ++i) {
-        const at_instance &in = insts[i];
-        const InstPlan &q = p.ip[(size_t)i];
-        InstDev &d = host[(size_t)i];
-        d.L = in.n_locs; d.M = in.n_missions; d.V = in.n_vehicles;
-        d.T = in.travel; d.p = in.pickup; d.d = in.delivery; d.b = in.vehicle_loc;
-        d.exit_loc = (int32_t *)(ws + q.exit_loc);
-        d.enter_loc = (int32_t *)(ws + q.enter_loc);
-        d.mrow = (int32_t *)(ws + q.mrow);
-        d.mcol = (int32_t *)(ws + q.mcol);
-        d.vrow = (int32_t *)(ws + q.vrow);
-        d.vcol = (int32_t *)(ws + q.vcol);
-        d.tc = (void *)(ws + q.tc);
-        d.tc_cap = q.tc_cap;
-        d.status = AT_EDEVICE;
-    }
-    InstDev *dev = (InstDev *)(ws + p.insts);
     hipError_t e = hipMemcpyAsync(dev, host.data(), sizeof(InstDev) * (size_t)n_inst,
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "upload instances");
@@ -157,7 +189,7 @@ static int prepare(int32_t n_inst, const at_instance *insts, char *ws, const WsP
         if (d.status == AT_EINVAL)
             return fail(AT_EINVAL, "instance %d: mission or vehicle location out of range, or pickup == delivery", i);
         if (d.status == AT_ERANGE)
-            return fail(AT_ERANGE, "instance %d: travel time outside [0, 2^27)", i);
+            return fail(AT_ERANGE, "instance %d: travel time outside [0, 2^23)", i);
         if (d.status != AT_OK) return fail(AT_EDEVICE, "instance %d: prepare status %d", i, d.status);
     }
     return AT_OK;
@@ -166,16 +198,6 @@ static int prepare(int32_t n_inst, const at_instance *insts, char *ws, const WsP
 // ---------------------------------------------------------------------------
 // schedule
 // ---------------------------------------------------------------------------
-struct JobHost {
-    int inst;
-    at_params pr;
-    uint64_t seed;
-    at_result *out;
-    int64_t slots;
-    uint32_t lds;
-    int tb16, esz16, block, chunk;
-};
-
 static int pick_chunk(const at_params &pr, int64_t M)
 {
     if (pr.chunk) return pr.chunk;
@@ -190,7 +212,40 @@ static int pick_block(const at_params &pr, int64_t slots)
     return 256;
 }
 
-static int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal)
+int plan_job(JobHost &h, const InstDev &d, bool alone)
+{
+    h.slots = n_slots(d.M, d.V);
+    h.tb16 = tabu_bytes(h.pr) == 2 ? 1 : 0;
+    h.esz16 = d.esz == 2 ? 1 : 0;
+    h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
+    h.block = pick_block(h.pr, h.slots);
+    h.chunk = pick_chunk(h.pr, d.M);
+    h.groups = 1;
+    if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit) {
+        if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
+        h.kind = AT_SCHED_GLOBAL;
+        h.block = h.pr.block ? h.pr.block : 256;
+        const int cap = max_groups_global(h.block, h.tb16, h.esz16);
+        if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
+        const int g = h.pr.n_groups ? h.pr.n_groups
+                                    : (int)std::max<int64_t>(1, std::min<int64_t>(num_cus(), h.slots / 16384));
+        h.groups = std::max(1, std::min(g, cap));
+        return AT_OK;
+    }
+    h.kind = AT_SCHED_WG;
+    if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
+        const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
+        int g = h.pr.n_groups ? h.pr.n_groups
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(32, h.slots / 8192));
+        g = std::min(g, std::min(cap, num_cus()));
+        if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
+        h.kind = AT_SCHED_MULTI;
+        h.groups = g;
+    }
+    return AT_OK;
+}
+
+int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal)
 {
     std::memset(&j, 0, sizeof(j));
     j.inst = dev_inst;
@@ -204,123 +259,199 @@ static int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobSca
     j.tb16 = h.tb16;
     j.chunk = h.chunk;
     j.seed = h.seed;
-    j.out_off = h.out->route_off;
-    j.out_seq = h.out->route_seq;
-    j.out_of = h.out->route_of;
+    j.out_off = h.out.route_off;
+    j.out_seq = h.out.route_seq;
+    j.out_of = h.out.route_of;
     if (j.trace) {
-        j.tr_move = h.out->tr_move;
-        j.tr_delta = h.out->tr_delta;
-        j.tr_obj = h.out->tr_obj;
-        j.tr_flags = h.out->tr_flags;
+        j.tr_move = h.out.tr_move;
+        j.tr_delta = h.out.tr_delta;
+        j.tr_obj = h.out.tr_obj;
+        j.tr_flags = h.out.tr_flags;
         if (h.pr.max_iters > 0 && (!j.tr_move || !j.tr_delta || !j.tr_obj || !j.tr_flags))
             return fail(AT_EINVAL, "trace requested but a trace array is null");
     }
     j.scal = scal;
     j.st = nullptr;
+    j.gb = h.gstate;
     return AT_OK;
 }
 
-static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, char *ws,
-                    const WsPlan &p, hipStream_t s)
+// Upload GlobalBufs pointer tables for the jobs on the global schedule.
+int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s)
 {
-    const uint32_t lds_max = max_lds_bytes() - 64;
-    const InstDev *dev_insts = (const InstDev *)(ws + p.insts);
-    JobDev *dj = (JobDev *)(ws + p.jobs);
-    JobScal *ds = (JobScal *)(ws + p.scal);
-    Xchg *xs = (Xchg *)(ws + p.xchg);
-    const int n = (int)jobs.size();
-    for (auto &h : jobs) {
-        const InstDev &d = ih[(size_t)h.inst];
-        h.slots = n_slots(d.M, d.V);
-        h.tb16 = ((int64_t)h.pr.max_iters + h.pr.tenure + 1 <= 65535) ? 1 : 0;
-        h.esz16 = d.esz == 2 ? 1 : 0;
-        h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
-        h.block = pick_block(h.pr, h.slots);
-        h.chunk = pick_chunk(h.pr, d.M);
-        if (h.lds > lds_max)
-            return fail(AT_ENOMEM, "instance %d needs %u bytes of LDS (limit %u); larger instances "
-                        "need the HBM-resident schedule", h.inst, h.lds, lds_max);
-        if (h.pr.schedule == AT_SCHED_GLOBAL)
-            return fail(AT_EINVAL, "the HBM-resident schedule is not available");
+    for (const auto &h : jobs) {
+        if (h.kind != AT_SCHED_GLOBAL) continue;
+        GlobalBufs g;
+        carve_gstate(g, ih[(size_t)h.inst].M, ih[(size_t)h.inst].V, h.tb16 ? 2 : 4, (char *)h.gstate);
+        hipError_t e = hipMemcpyAsync(h.gstate, &g, sizeof(g), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "upload state tables");
+        // a synchronous copy source must stay alive until the copy is done
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "upload state tables");
     }
-    // order: by kernel class (entry width, tabu width), then largest first; the
-    // queue of each class hands its jobs out in this order
-    std::vector<int> order((size_t)n);
-    for (int k = 0; k < n; ++k) order[(size_t)k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const JobHost &x = jobs[(size_t)a], &y = jobs[(size_t)b];
-        const int cx = x.esz16 * 2 + x.tb16, cy = y.esz16 * 2 + y.tb16;
-        if (cx != cy) return cx < cy;
-        return x.slots > y.slots;
-    });
-    std::vector<JobDev> hj((size_t)n);
-    for (int k = 0; k < n; ++k) {
-        const JobHost &h = jobs[(size_t)order[(size_t)k]];
-        int rc = fill_job(hj[(size_t)k], h, dev_insts + h.inst, ds + order[(size_t)k]);
-        if (rc) return rc;
-    }
-    hipError_t e = hipMemcpyAsync(dj, hj.data(), sizeof(JobDev) * (size_t)n, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "upload jobs");
-    if ((e = fill_u32((uint32_t *)ds, 0u, sizeof(JobScal) * (size_t)n / 4, s)) != hipSuccess)
-        return hip_fail(e, "clear results");
+    return AT_OK;
+}
 
-    const JobHost &h0 = jobs[(size_t)order[0]];
-    bool multi = false;
-    int groups = 1;
-    if (n == 1) {
-        if (h0.pr.schedule == AT_SCHED_MULTI) multi = true;
-        if (h0.pr.schedule == AT_SCHED_AUTO && h0.slots >= 20000) multi = true;
-        if (multi) {
-            const int cap = max_groups_multi(h0.block, h0.lds, h0.tb16, h0.esz16);
-            groups = h0.pr.n_groups ? h0.pr.n_groups
-                                    : (int)std::max<int64_t>(1, std::min<int64_t>(64, h0.slots / 4096));
-            groups = std::min(groups, std::min(cap, num_cus()));
-            if (groups < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
-        }
-    }
-    if (multi) {
-        if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
-        if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
-        if ((e = launch_search_multi(dj, xs, groups, h0.block, h0.lds, h0.tb16, h0.esz16, s)) != hipSuccess)
-            return hip_fail(e, "multi-workgroup search launch");
-    } else {
-        // one launch per kernel class, LDS sized for its largest job
-        int k = 0;
-        while (k < n) {
-            const JobHost &hf = jobs[(size_t)order[(size_t)k]];
+// Launch every job of `dj` (device table in the order of `order`).  Jobs of
+// the one-workgroup schedule share one persistent launch per kernel class;
+// multi-workgroup and HBM-resident jobs get a cooperative launch each.
+int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
+                Xchg *xs, hipStream_t s)
+{
+    hipError_t e;
+    const int n = (int)order.size();
+    int k = 0;
+    while (k < n) {
+        const JobHost &hf = jobs[(size_t)order[(size_t)k]];
+        if (hf.kind == AT_SCHED_WG) {
             int k1 = k, block = 256;
             uint32_t lds = 0;
             while (k1 < n) {
                 const JobHost &h = jobs[(size_t)order[(size_t)k1]];
-                if (h.esz16 != hf.esz16 || h.tb16 != hf.tb16) break;
+                if (h.kind != AT_SCHED_WG || h.esz16 != hf.esz16 || h.tb16 != hf.tb16) break;
                 lds = std::max(lds, h.lds);
                 block = std::max(block, h.block);
                 ++k1;
             }
             const int count = k1 - k;
             if ((e = fill_u32(&xs->queue, 0u, 1, s)) != hipSuccess) return hip_fail(e, "reset queue");
-            const int per_cu = std::max(1, (int)((160 * 1024) / std::max<uint32_t>(lds, 1)));
+            const int per_cu = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(lds, 1)));
             const int grid = std::max(1, std::min(count, num_cus() * std::min(per_cu, 8)));
             if ((e = launch_search_wg(dj + k, count, xs, grid, block, lds, hf.tb16, hf.esz16, s)) != hipSuccess)
                 return hip_fail(e, "search launch");
             k = k1;
+            continue;
         }
+        if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
+        if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
+        if (hf.kind == AT_SCHED_MULTI)
+            e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
+        else
+            e = launch_search_global(dj + k, xs, hf.groups, hf.block, hf.tb16, hf.esz16, s);
+        if (e != hipSuccess) return hip_fail(e, "cooperative search launch");
+        ++k;
     }
+    return AT_OK;
+}
+
+// Order jobs: one-workgroup jobs grouped by kernel class, largest first (the
+// queue of each class hands its jobs out in this order), then the rest.
+std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
+{
+    const int n = (int)jobs.size();
+    std::vector<int> order((size_t)n);
+    for (int k = 0; k < n; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const JobHost &x = jobs[(size_t)a], &y = jobs[(size_t)b];
+        const int cx = x.kind == AT_SCHED_WG ? x.esz16 * 2 + x.tb16 : 4 + x.kind;
+        const int cy = y.kind == AT_SCHED_WG ? y.esz16 * 2 + y.tb16 : 4 + y.kind;
+        if (cx != cy) return cx < cy;
+        return x.slots > y.slots;
+    });
+    return order;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&a);
+        return e != hipSuccess ? e : hipEventCreate(&b);
+    }
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, char *ws,
+                    const WsPlan &p, hipStream_t s, at_result *const *outs)
+{
+    const InstDev *dev_insts = (const InstDev *)(ws + p.insts);
+    JobDev *dj = (JobDev *)(ws + p.jobs);
+    JobScal *ds = (JobScal *)(ws + p.scal);
+    Xchg *xs = (Xchg *)(ws + p.xchg);
+    const int n = (int)jobs.size();
+    for (auto &h : jobs) {
+        int rc = plan_job(h, ih[(size_t)h.inst], n == 1);
+        if (rc) return rc;
+    }
+    int rc = upload_gstates(jobs, ih, s);
+    if (rc) return rc;
+    const std::vector<int> order = order_jobs(jobs);
+    std::vector<JobDev> hj((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        const JobHost &h = jobs[(size_t)order[(size_t)k]];
+        rc = fill_job(hj[(size_t)k], h, dev_insts + h.inst, ds + order[(size_t)k]);
+        if (rc) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(dj, hj.data(), sizeof(JobDev) * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload jobs");
+    if ((e = fill_u32((uint32_t *)ds, 0u, sizeof(JobScal) * (size_t)n / 4, s)) != hipSuccess)
+        return hip_fail(e, "clear results");
+    EventPair ev;
+    if ((e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
+    if ((e = hipEventRecord(ev.a, s)) != hipSuccess) return hip_fail(e, "event record");
+    rc = launch_jobs(jobs, order, dj, xs, s);
+    if (rc) return rc;
+    if ((e = hipEventRecord(ev.b, s)) != hipSuccess) return hip_fail(e, "event record");
     std::vector<JobScal> hs((size_t)n);
     if ((e = hipMemcpyAsync(hs.data(), ds, sizeof(JobScal) * (size_t)n, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "read back results");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
-    int rc = AT_OK;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess) return hip_fail(e, "event time");
+    rc = AT_OK;
     for (int k = 0; k < n; ++k) {
-        at_result *o = jobs[(size_t)k].out;
+        at_result *o = outs[k];
+        o->search_ms = ms;
         o->best_obj = hs[(size_t)k].best_obj;
         o->final_obj = hs[(size_t)k].final_obj;
         o->iters_done = hs[(size_t)k].iters_done;
         o->best_iter = hs[(size_t)k].best_iter;
         o->status = hs[(size_t)k].status;
-        if (o->status != AT_OK && rc == AT_OK) rc = fail(AT_EDEVICE, "solve %d failed on the device (status %d)", k, o->status);
+        if (o->status != AT_OK && rc == AT_OK)
+            rc = fail(AT_EDEVICE, "solve %d failed on the device (status %d)", k, o->status);
     }
     return rc;
+}
+
+static int solve_common(int32_t n_inst, const at_instance *insts, const at_params *params,
+                        int32_t n_restarts, void *ws, size_t ws_bytes, void *stream, at_result *out,
+                        bool single)
+{
+    for (int32_t i = 0; i < n_inst; ++i) {
+        int rc = check_scalars(&insts[i], &params[i]);
+        if (rc) return rc;
+    }
+    if (!ws) return fail(AT_EINVAL, "null workspace");
+    const int64_t nj = (int64_t)n_inst * n_restarts;
+    if (nj > (1 << 24)) return fail(AT_EINVAL, "too many solves in one call");
+    for (int64_t k = 0; k < nj; ++k)
+        if (!out[k].route_off || (insts[k / n_restarts].n_missions > 0 && !out[k].route_seq))
+            return fail(AT_EINVAL, "solve %lld: null route output", (long long)k);
+    WsPlan p = plan_ws(n_inst, insts, params, n_restarts);
+    if (ws_bytes < p.end) return fail(AT_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, p.end);
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    std::vector<InstDev> ih((size_t)n_inst);
+    for (int32_t i = 0; i < n_inst; ++i) carve_inst(ih[(size_t)i], insts[i], base + p.inst_off[(size_t)i]);
+    int rc = prepare_instances(n_inst, (InstDev *)(base + p.insts), ih, s);
+    if (rc) return rc;
+    std::vector<JobHost> jobs((size_t)nj);
+    std::vector<at_result *> outs((size_t)nj);
+    for (int64_t k = 0; k < nj; ++k) {
+        const int i = (int)(k / n_restarts), r = (int)(k % n_restarts);
+        JobHost &h = jobs[(size_t)k];
+        h.inst = i;
+        h.pr = params[i];
+        h.seed = single ? params[i].restart_seed : (r == 0 ? 0 : params[i].restart_seed + (uint64_t)r);
+        h.out = out[k];
+        h.gstate = p.gstate_off[(size_t)k] ? (GlobalBufs *)(base + p.gstate_off[(size_t)k]) : nullptr;
+        if (nj > 1 && h.pr.schedule == AT_SCHED_MULTI) h.pr.schedule = AT_SCHED_AUTO;
+        outs[(size_t)k] = &out[k];
+    }
+    return run_jobs(jobs, ih, base, p, s, outs.data());
 }
 
 }  // namespace at
@@ -329,7 +460,7 @@ using namespace at;
 
 extern "C" {
 
-const char *at_last_error(void) { return g_err.c_str(); }
+const char *at_last_error(void) { return last_error(); }
 
 int at_build_travel(int32_t n, const double *lat_deg, const double *lon_deg, double speed_kmh,
                     int32_t *travel, void *stream)
@@ -347,10 +478,8 @@ size_t at_workspace_size(int32_t n_inst, const at_instance *insts, const at_para
     if (n_inst < 1 || !insts || !params || n_restarts < 1) return 0;
     for (int32_t i = 0; i < n_inst; ++i)
         if (check_scalars(&insts[i], &params[i]) != AT_OK) return 0;
-    const int64_t jobs = (int64_t)n_inst * n_restarts;
-    if (jobs > INT32_MAX) return 0;
-    WsPlan p = plan_ws(n_inst, insts, (int32_t)jobs, false);
-    return p.end;
+    if ((int64_t)n_inst * n_restarts > (1 << 24)) return 0;
+    return plan_ws(n_inst, insts, params, n_restarts).end;
 }
 
 int at_solve_batch(int32_t n_inst, const at_instance *insts, const at_params *params,
@@ -358,56 +487,14 @@ int at_solve_batch(int32_t n_inst, const at_instance *insts, const at_params *pa
 {
     if (n_inst < 1 || !insts || !params || !out || n_restarts < 1)
         return fail(AT_EINVAL, "bad batch arguments");
-    if (!ws) return fail(AT_EINVAL, "null workspace");
-    for (int32_t i = 0; i < n_inst; ++i) {
-        int rc = check_scalars(&insts[i], &params[i]);
-        if (rc) return rc;
-    }
-    const int64_t nj = (int64_t)n_inst * n_restarts;
-    if (nj > INT32_MAX) return fail(AT_EINVAL, "too many solves");
-    WsPlan p = plan_ws(n_inst, insts, (int32_t)nj, false);
-    if (ws_bytes < p.end) return fail(AT_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, p.end);
-    for (int64_t k = 0; k < nj; ++k)
-        if (!out[k].route_off || (insts[k / n_restarts].n_missions > 0 && !out[k].route_seq))
-            return fail(AT_EINVAL, "solve %lld: null route output", (long long)k);
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<InstDev> ih;
-    int rc = prepare(n_inst, insts, (char *)ws, p, s, ih);
-    if (rc) return rc;
-    std::vector<JobHost> jobs((size_t)nj);
-    for (int64_t k = 0; k < nj; ++k) {
-        const int i = (int)(k / n_restarts), r = (int)(k % n_restarts);
-        JobHost &h = jobs[(size_t)k];
-        h.inst = i;
-        h.pr = params[i];
-        h.seed = r == 0 ? 0 : params[i].restart_seed + (uint64_t)r;
-        h.out = &out[k];
-    }
-    if (nj > 1)
-        for (auto &h : jobs) if (h.pr.schedule == AT_SCHED_MULTI) h.pr.schedule = AT_SCHED_AUTO;
-    return run_jobs(jobs, ih, (char *)ws, p, s);
+    return solve_common(n_inst, insts, params, n_restarts, ws, ws_bytes, stream, out, false);
 }
 
 int at_solve(const at_instance *inst, const at_params *params, void *ws, size_t ws_bytes,
              void *stream, at_result *out)
 {
     if (!inst || !params || !out) return fail(AT_EINVAL, "null argument");
-    int rc = check_scalars(inst, params);
-    if (rc) return rc;
-    if (!ws) return fail(AT_EINVAL, "null workspace");
-    if (!out->route_off || (inst->n_missions > 0 && !out->route_seq)) return fail(AT_EINVAL, "null route output");
-    WsPlan p = plan_ws(1, inst, 1, false);
-    if (ws_bytes < p.end) return fail(AT_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, p.end);
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<InstDev> ih;
-    rc = prepare(1, inst, (char *)ws, p, s, ih);
-    if (rc) return rc;
-    std::vector<JobHost> jobs(1);
-    jobs[0].inst = 0;
-    jobs[0].pr = *params;
-    jobs[0].seed = params->restart_seed;
-    jobs[0].out = out;
-    return run_jobs(jobs, ih, (char *)ws, p, s);
+    return solve_common(1, inst, params, 1, ws, ws_bytes, stream, out, true);
 }
 
 int at_debug_eval_moves(const at_instance *inst, const at_params *params, const int32_t *route_off,
@@ -419,31 +506,33 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     if (rc) return rc;
     if (!route_off || !tabu_until || !keys_out || !ws) return fail(AT_EINVAL, "null pointer");
     if (inst->n_missions < 1) return AT_OK;
-    WsPlan p = plan_ws(1, inst, 1, false);
+    WsPlan p = plan_ws(1, inst, params, 1);
     if (ws_bytes < p.end) return fail(AT_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, p.end);
     hipStream_t s = (hipStream_t)stream;
-    std::vector<InstDev> ih;
-    rc = prepare(1, inst, (char *)ws, p, s, ih);
+    char *base = (char *)ws;
+    std::vector<InstDev> ih(1);
+    carve_inst(ih[0], *inst, base + p.inst_off[0]);
+    rc = prepare_instances(1, (InstDev *)(base + p.insts), ih, s);
     if (rc) return rc;
     const InstDev &d = ih[0];
     const uint32_t lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, 4).total;
-    if (lds > max_lds_bytes() - 64) return fail(AT_ENOMEM, "instance too large for the LDS-resident key dump");
+    if (lds > kLdsLimit) return fail(AT_ENOMEM, "instance too large for the LDS-resident key dump");
     JobHost h;
     h.inst = 0;
     h.pr = *params;
-    h.seed = 0;
-    at_result dummy;
-    std::memset(&dummy, 0, sizeof(dummy));
-    dummy.route_off = (int32_t *)route_off;
-    dummy.route_seq = (int32_t *)route_seq;
-    h.out = &dummy;
     h.pr.trace = 0;
+    h.seed = 0;
+    std::memset(&h.out, 0, sizeof(h.out));
+    h.out.route_off = (int32_t *)route_off;
+    h.out.route_seq = (int32_t *)route_seq;
     h.slots = n_slots(d.M, d.V);
     h.chunk = pick_chunk(*params, d.M);
+    h.tb16 = 0;
+    h.gstate = nullptr;
     JobDev j;
-    rc = fill_job(j, h, (const InstDev *)((char *)ws + p.insts), (JobScal *)((char *)ws + p.scal));
+    rc = fill_job(j, h, (const InstDev *)(base + p.insts), (JobScal *)(base + p.scal));
     if (rc) return rc;
-    JobDev *dj = (JobDev *)((char *)ws + p.jobs);
+    JobDev *dj = (JobDev *)(base + p.jobs);
     hipError_t e = hipMemcpyAsync(dj, &j, sizeof(JobDev), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "upload job");
     const int block = params->block ? params->block : 256;

@@ -22,13 +22,19 @@
 //   rt[i]    vehicle of flat position i
 //   pof[m], rof[m]  flat position / vehicle of mission m
 //   tabu[v*M + m] = 1 + last iteration at which m may not enter v (0 = never)
-// Per-iteration arrays (rebuilt from the state every iteration):
-//   per position i: xr = exit row offset of the predecessor (or base),
-//                   yc = entry column of the successor (or base),
-//                   outv = T[xr][p_m] + T[d_m][yc], link = T[xr][yc]
-//   per gap G (G = i + rt[i] is the gap before position i, G = off[v+1] + v
-//   the gap before vehicle v's return): ga = exit row offset on its left,
-//   gb = entry column on its right, gc = T[ga][gb], gr = its vehicle.
+// Per-iteration arrays (rebuilt from the state every iteration), 16-byte
+// records so that one LDS broadcast read brings a whole column to a wavefront:
+//   posA[i] = {mrow, mcol of the mission at i, xr, yc}
+//             xr = exit row offset of its predecessor (or the base),
+//             yc = entry column of its successor (or the base)
+//   posB[i] = {outv, link, mission | vehicle << 16, rank}
+//             outv = T[xr][p] + T[d][yc], link = T[xr][yc], rank = rank of the
+//             mission id among the positions of its column chunk
+//   gap[G]  = {ga, gb, gc, gr}: G = i + rt[i] is the gap before position i and
+//             G = off[v+1] + v the gap before vehicle v's return; ga = exit row
+//             offset on its left, gb = entry column on its right, gc = T[ga][gb],
+//             gr = its vehicle
+//   prank[c*chunk + k] = position (within chunk c) of the mission of rank k
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,7 +46,7 @@ namespace at {
 constexpr int kWave = 64;
 constexpr uint64_t kKeyNone = ~0ull;
 constexpr int32_t kDeltaBias = 1 << 30;
-constexpr int32_t kMaxTravel = 1 << 27;       // travel times must be below this
+constexpr int32_t kMaxTravel = 1 << 23;       // travel times must be below this (97 days)
 constexpr int kMaxLocs = 65535;
 constexpr int kMaxMissions = 65535;
 constexpr int kMaxVehicles = 65535;
@@ -73,6 +79,19 @@ struct SolveState {
     int32_t t, best_iter, stopped, valid;
 };
 
+// HBM-resident state of one solve (the global schedule): the route arrays
+// are double-buffered so that every workgroup can write the next iteration's
+// routes while others still read the current ones.
+struct GlobalBufs {
+    uint16_t *seq[2], *rt[2], *pof[2], *rof[2];
+    int32_t *off[2];
+    int4 *posA, *posB, *gap;
+    uint8_t *prank;
+    void *tabu;
+    int32_t cur;                      // which buffer holds the current routes
+    int32_t pad;
+};
+
 struct JobDev {
     const InstDev *inst;
     int32_t variant, tenure, max_iters, aspiration, trace;
@@ -89,20 +108,22 @@ struct JobDev {
     uint8_t *tr_flags;
     JobScal *scal;
     SolveState *st;
+    GlobalBufs *gb;                   // global schedule only
 };
 
 // Cross-workgroup exchange for the multi-workgroup schedules.
 struct Xchg {
     uint64_t key[3];
-    uint32_t cnt;
-    uint32_t abort;
-    uint32_t queue;
+    uint32_t cnt;                     // grid-barrier arrivals (monotone within a launch)
+    uint32_t abort;                   // set by a workgroup whose wait ran out
+    uint32_t queue;                   // next job of the one-workgroup-per-job schedule
     uint32_t pad[3];
+    int64_t init_obj;                 // greedy objective, published by workgroup 0
 };
 
 struct Lay {
     uint32_t tc, mrow, mcol, vrow, vcol, off, seq, rt, rof, pof;
-    uint32_t xr, yc, outv, link, ga, gb, gc, gr, tabu, red, total;
+    uint32_t posA, posB, gap, prank, tabu, red, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
@@ -123,16 +144,12 @@ __host__ __device__ inline Lay lds_layout(int M, int V, int R, int Cs, int esz, 
     AT_TAKE(rt, 2 * uM);
     AT_TAKE(rof, 2 * uM);
     AT_TAKE(pof, 2 * uM);
-    AT_TAKE(xr, 4 * uM);
-    AT_TAKE(yc, 4 * uM);
-    AT_TAKE(outv, 4 * NG);      // also greedy scratch (needs max(M, V))
-    AT_TAKE(link, 4 * NG);
-    AT_TAKE(ga, 4 * NG);
-    AT_TAKE(gb, 4 * NG);
-    AT_TAKE(gc, 4 * NG);
-    AT_TAKE(gr, 2 * NG);
+    AT_TAKE(posA, 16 * uM);
+    AT_TAKE(posB, 16 * uM);
+    AT_TAKE(gap, 16 * NG);
+    AT_TAKE(prank, uM);
     AT_TAKE(tabu, (uint64_t)tbsz * uM * uV);
-    AT_TAKE(red, 512);
+    AT_TAKE(red, 1024);
 #undef AT_TAKE
     l.total = o;
     return l;
@@ -157,7 +174,16 @@ __host__ __device__ inline int64_t compact_bound(int L, int M, int V)
     return r < L ? r : L;
 }
 
-inline int64_t n_slots(int64_t M, int64_t V) { return M * (M + V) + M * (M - 1) / 2; }
+// Bytes of the HBM state of one solve on the global schedule (GlobalBufs arrays).
+__host__ __device__ inline uint64_t global_state_bytes(int M, int V, int tbsz)
+{
+    const uint64_t uM = (uint64_t)M, uV = (uint64_t)V, NG = uM + uV;
+    auto a = [](uint64_t x) { return (x + 255u) & ~(uint64_t)255u; };
+    return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * a(16 * uM) + a(16 * NG) + a(uM)
+         + a((uint64_t)tbsz * uM * uV);
+}
+
+__host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M + V) + M * (M - 1) / 2; }
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_travel(int32_t n, const double *lat, const double *lon, double speed,
@@ -167,6 +193,9 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, Xchg *xs, int gr
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
+hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block, int tb16,
+                                int esz16, hipStream_t s);
+int max_groups_global(int block, int tb16, int esz16);
 hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_t *seq,
                              const int32_t *tabu_until, int32_t t, int64_t cur, int64_t best,
                              uint64_t *keys, int block, uint32_t lds_bytes, int esz16,

@@ -1,0 +1,51 @@
+// engine.h -- host-side pieces shared by the solve/batch API (api.hip) and the
+// serving loop (server.hip): argument checks, workspace carving, instance
+// preparation, schedule choice and launches.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "atabu.h"
+#include "atabu_internal.h"
+
+namespace at {
+
+// LDS a workgroup may use on gfx950 (160 KiB), minus room for static LDS.
+constexpr uint32_t kLdsLimit = 160u * 1024u - 64u;
+
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One solve as the host plans it.
+struct JobHost {
+    int inst = 0;
+    at_params pr{};
+    uint64_t seed = 0;
+    at_result out{};
+    int64_t slots = 0;
+    uint32_t lds = 0;
+    int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
+    int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
+    GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+const char *last_error();
+int check_scalars(const at_instance *in, const at_params *pr);
+int tabu_bytes(const at_params &pr);
+bool may_need_global(const at_instance &in, const at_params &pr);
+size_t inst_bytes(const at_instance &in);
+size_t gstate_bytes(const at_instance &in, const at_params &pr);
+void carve_inst(InstDev &d, const at_instance &in, char *base);
+void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base);
+int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s);
+int plan_job(JobHost &h, const InstDev &d, bool alone);
+int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal);
+int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s);
+int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
+                Xchg *xs, hipStream_t s);
+std::vector<int> order_jobs(const std::vector<JobHost> &jobs);
+
+}  // namespace at

@@ -2,7 +2,7 @@
 //
 // One workgroup per instance:
 //   1. check every mission (pickup, delivery inside [0, L), pickup != delivery)
-//      and vehicle base, and every travel time inside [0, 2^27);
+//      and vehicle base, and every travel time inside [0, 2^23);
 //   2. mark the exit locations (deliveries, bases) and entry locations
 //      (pickups, bases) in LDS bitmaps and rank them by a prefix sum of
 //      popcounts, so both are numbered in increasing location order;

@@ -4,27 +4,31 @@
 // Each iteration (Algorithm 3 in the best-move form; Algorithm 2 when the tabu
 // rules are off):
 //   prep    from the routes, every position's neighbours and every gap's ends
-//           (O(M+V), one item per thread)
+//           as 16-byte records (O(M+V), one item per thread)
 //   eval    every relocate move (mission -> gap) and every swap of two missions
-//           gets its cost delta, a tabu bit (the move puts a mission into a
-//           vehicle it left within `tenure` iterations and does not beat the
-//           best objective) and is packed into a 64-bit key
-//              blocked << 63 | (delta + 2^30) << 32 | slot index,
-//           so the smallest key is the best admissible move, ties going to the
-//           smallest index; each lane keeps a running minimum, then wavefront
-//           shuffles and one LDS pass give the workgroup minimum (and, with
-//           several workgroups per solve, a 64-bit atomic minimum in HBM)
+//           gets its cost delta; the move is blocked if it puts a mission into
+//           a vehicle it left within `tenure` iterations and does not beat the
+//           best objective (aspiration); the best move is the smallest 64-bit
+//              blocked << 63 | (delta + 2^30) << 32 | slot index
 //   apply   every thread decodes the winner; the flat route array is shifted in
 //           two LDS phases; the moved missions become tabu for the vehicles
 //           they left; the trace record and, on a new best, the routes are
 //           written out.
 //
-// Work layout of eval: lanes own 64 consecutive route positions (a "tile"),
-// each lane one mission, and walk the columns of a unit -- a run of `chunk`
-// gaps (relocate) or partner positions (swap) -- so the per-column values are
-// wave-uniform broadcasts and the per-lane values stay in registers.  The two
-// gathers of a relocate and four of a swap hit the compact travel block in
-// LDS.  Units are dealt round-robin to every wavefront of the solve.
+// Work layout of eval.  Lanes own 64 consecutive route positions (a tile), one
+// mission each, whose values stay in registers; a unit is a run of `chunk`
+// columns -- gaps (relocate) or partner positions (swap) -- read as LDS
+// broadcasts.  Units are dealt round-robin to every wavefront of the solve.
+// Within a unit the columns are cut at vehicle boundaries; inside a segment
+// the tabu status of a relocate depends only on (mission, vehicle), so each
+// lane keeps a 32-bit running minimum of (delta + 2^25) << 6 | column rank and
+// turns it into a 64-bit key once per segment (a blocked move can only win a
+// segment if every move of the segment with the same or smaller delta is
+// blocked too, since aspiration only depends on the delta).  Swaps keep two
+// such minima (tabu / not tabu) per segment.  Column ranks follow the slot
+// index order for a fixed lane: the gap offset for relocates, the partner's
+// mission id for swaps (ranked inside the chunk by prep), so ties resolve to
+// the smallest slot index exactly as the full 64-bit comparison would.
 #include "atabu_internal.h"
 #include "atabu.h"
 
@@ -32,14 +36,15 @@ namespace at {
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int32_t kPackBias = 1 << 25;       // |delta| < 4 * 2^23
 
 struct Ctx {
     int32_t *mrow, *mcol, *vrow, *vcol, *off;
     uint16_t *seq, *rt, *rof, *pof;
-    int32_t *xr, *yc, *outv, *link, *ga, *gb, *gc;
-    uint16_t *gr;
+    int4 *posA, *posB, *gap;
+    uint8_t *prank;
     uint64_t *red;
-    int M, V, NG;
+    int M, V, NG, chunk;
     uint32_t R;   // relocate slots M*(M+V)
 };
 
@@ -62,6 +67,12 @@ __device__ __forceinline__ uint64_t pack_key(bool blocked, int delta, uint32_t i
     return ((uint64_t)blocked << 63) | ((uint64_t)(uint32_t)(delta + kDeltaBias) << 32) | idx;
 }
 
+__device__ __forceinline__ uint32_t swap_index(uint32_t R, uint32_t M, uint32_t a, uint32_t b)
+{
+    // a < b
+    return R + a * M - (a * (a + 1u)) / 2u + (b - a - 1u);
+}
+
 __device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t k)
 {
     uint64_t z = seed + k * kGamma;
@@ -82,106 +93,153 @@ __device__ __forceinline__ int route_of_pos(const int32_t *off, int V, int k)
 }
 
 // ---------------------------------------------------------------------------
-// prep: per-position neighbours and per-gap ends of the current routes
+// prep: per-position neighbours, per-gap ends, per-chunk ranks
 // ---------------------------------------------------------------------------
 template <typename TE>
 __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nthr)
 {
+    const int CH = c.chunk;
     for (int i = tid; i < c.M; i += nthr) {
         const int m = c.seq[i], r = c.rt[i];
         const int x = (i == c.off[r]) ? c.vrow[r] : c.mrow[c.seq[i - 1]];
         const int y = (i + 1 == c.off[r + 1]) ? c.vcol[r] : c.mcol[c.seq[i + 1]];
         const int mc = c.mcol[m], mr = c.mrow[m];
         const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
-        c.xr[i] = x;
-        c.yc[i] = y;
-        c.outv[i] = a + bb;
-        c.link[i] = l;
-        const int G = i + r;
-        c.ga[G] = x;
-        c.gb[G] = mc;
-        c.gc[G] = a;
-        c.gr[G] = (uint16_t)r;
+        // rank of m among the missions of this position's chunk
+        const int base = i - i % CH, end = min(c.M, base + CH);
+        int rank = 0;
+        for (int j = base; j < end; ++j) rank += c.seq[j] < m ? 1 : 0;
+        c.prank[base + rank] = (uint8_t)(i - base);
+        c.posA[i] = make_int4(mr, mc, x, y);
+        c.posB[i] = make_int4(a + bb, l, m | (r << 16), rank);
+        c.gap[i + r] = make_int4(x, mc, a, r);
     }
     for (int r = tid; r < c.V; r += nthr) {
-        const int e = c.off[r + 1], G = e + r;
+        const int e = c.off[r + 1];
         const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
-        c.ga[G] = x;
-        c.gb[G] = c.vcol[r];
-        c.gc[G] = tc[x + c.vcol[r]];
-        c.gr[G] = (uint16_t)r;
+        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]], r);
     }
 }
 
 // ---------------------------------------------------------------------------
-// eval units
+// eval: relocate unit (columns G0..G1 of one tile)
 // ---------------------------------------------------------------------------
-template <typename TE, typename TB, bool DBG>
+template <typename TE, typename TB>
 __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, const TB *tabu,
-                                                  int tl, int G0, int G1, int lane, int t,
-                                                  int thr, bool use_tabu, uint64_t *keys_out)
+                                                  int tl, int G0, int G1, int lane, int t, int thr,
+                                                  bool use_tabu, int rlo, int rhi)
 {
     const int i = tl * kWave + lane;
     const bool act = i < c.M;
-    const int ii = act ? i : 0;
-    const int m = c.seq[ii];
-    const int mr = c.mrow[m], mc = c.mcol[m];
-    const int rem = c.link[ii] - c.outv[ii];
-    const int Gi = ii + c.rt[ii];
+    const int ii = act ? i : tl * kWave;
+    const int4 pa = c.posA[ii], pb = c.posB[ii];
+    const int m = pb.z & 0xFFFF, ri = pb.z >> 16;
+    const int mr = pa.x, mc = pa.y;
+    const int remb = pb.y - pb.x + kPackBias;
+    const int Gi = ii + ri;
     const uint32_t ibase = (uint32_t)m * (uint32_t)c.NG;
     uint64_t best = kKeyNone;
-    for (int G = G0; G < G1; ++G) {
-        const int a = c.ga[G], b = c.gb[G], gcv = c.gc[G], r = c.gr[G];
-        const int d = rem + (int)tc[a + mc] + (int)tc[mr + b] - gcv;
-        const bool ok = act && (unsigned)(G - Gi) >= 2u;
+    int G = G0;
+    while (G < G1) {
+        const int r = c.gap[G].w;
+        const int Gend = min(G1, c.off[r + 1] + r + 1);
         const bool tb = use_tabu && (int)tabu[r * c.M + m] > t;
-        const bool blocked = tb && !(d < thr);
-        const uint64_t key = ok ? pack_key(blocked, d, ibase + (uint32_t)G) : kKeyNone;
-        if (DBG) {
-            if (act) keys_out[ibase + (uint32_t)G] = key;
+        uint32_t pm = 0xFFFFFFFFu;
+        if (r < rlo || r > rhi) {
+            // no lane of this tile flies vehicle r: no gap is a lane's own
+            for (; G < Gend; ++G) {
+                const int4 g = c.gap[G];
+                const int d = remb + (int)tc[g.x + mc] + (int)tc[mr + g.y] - g.z;
+                pm = min(pm, ((uint32_t)d << 6) | (uint32_t)(G - G0));
+            }
         } else {
-            best = umin64(best, key);
+            for (; G < Gend; ++G) {
+                const int4 g = c.gap[G];
+                const int d = remb + (int)tc[g.x + mc] + (int)tc[mr + g.y] - g.z;
+                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)(G - G0);
+                pm = ((unsigned)(G - Gi) >= 2u) ? min(pm, p) : pm;
+            }
+        }
+        if (act && pm != 0xFFFFFFFFu) {
+            const int d = (int)(pm >> 6) - kPackBias;
+            const int Gw = G0 + (int)(pm & 63u);
+            const bool blocked = tb && !(d < thr);
+            best = umin64(best, pack_key(blocked, d, ibase + (uint32_t)Gw));
         }
     }
     return best;
 }
 
-template <typename TE, typename TB, bool DBG>
-__device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const TB *tabu,
-                                              int tl, int j0, int j1, int lane, int t, int thr,
-                                              bool use_tabu, uint64_t *keys_out)
+// ---------------------------------------------------------------------------
+// eval: swap unit (partner positions j0..j1 of one tile, j0 a chunk start)
+// ---------------------------------------------------------------------------
+template <typename TE, typename TB>
+__device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const TB *tabu, int tl,
+                                              int j0, int j1, int lane, int t, int thr,
+                                              bool use_tabu)
 {
     const int i = tl * kWave + lane;
     const bool act = i < c.M;
-    const int ii = act ? i : 0;
-    const int mi = c.seq[ii];
-    const int mri = c.mrow[mi], mci = c.mcol[mi];
-    const int xri = c.xr[ii], yci = c.yc[ii], outi = c.outv[ii], ri = c.rt[ii];
+    const int ii = act ? i : tl * kWave;
+    const int4 pa = c.posA[ii], pb = c.posB[ii];
+    const int mi = pb.z & 0xFFFF, ri = pb.z >> 16;
+    const int mri = pa.x, mci = pa.y, xri = pa.z, yci = pa.w;
+    const int outb = kPackBias - pb.x;
     const uint32_t M = (uint32_t)c.M;
+    // partners at or before the lane, or directly after it, need the masked path
+    const bool diag = j0 <= tl * kWave + kWave;
+    const TB *tabu_ri = tabu + ri * c.M;
     uint64_t best = kKeyNone;
-    for (int j = j0; j < j1; ++j) {
-        const int mj = c.seq[j];
-        const int mrj = c.mrow[mj], mcj = c.mcol[mj];
-        const int xrj = c.xr[j], ycj = c.yc[j], outj = c.outv[j], rj = c.rt[j];
-        int d;
-        if (j == i + 1 && ri == rj) {
-            // i directly before j:  P i j N  ->  P j i N
-            d = (int)tc[xri + mcj] + (int)tc[mrj + mci] + (int)tc[mri + ycj]
-              - ((int)tc[xri + mci] + (int)tc[mri + mcj] + (int)tc[mrj + ycj]);
+    int j = j0;
+    while (j < j1) {
+        const int r = c.posB[j].z >> 16;
+        const int jend = min(j1, c.off[r + 1]);
+        const bool t1 = use_tabu && (int)tabu[r * c.M + mi] > t;
+        uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
+        if (!diag) {
+            for (; j < jend; ++j) {
+                const int4 a = c.posA[j], b = c.posB[j];
+                const int d = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
+                            + (int)tc[a.z + mci] + (int)tc[mri + a.w];
+                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)b.w;
+                const bool tb = t1 || (use_tabu && (int)tabu_ri[b.z & 0xFFFF] > t);
+                mT = tb ? min(mT, p) : mT;
+                mF = tb ? mF : min(mF, p);
+            }
         } else {
-            d = (int)tc[xri + mcj] + (int)tc[mrj + yci] + (int)tc[xrj + mci] + (int)tc[mri + ycj]
-              - outi - outj;
+            for (; j < jend; ++j) {
+                const int4 a = c.posA[j], b = c.posB[j];
+                int d;
+                if (j == i + 1 && ri == r) {
+                    // the lane's mission directly before the partner: P i j N -> P j i N
+                    d = kPackBias + (int)tc[xri + a.y] + (int)tc[a.x + mci] + (int)tc[mri + a.w]
+                      - ((int)tc[xri + mci] + (int)tc[mri + a.y] + (int)tc[a.x + a.w]);
+                } else {
+                    d = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
+                      + (int)tc[a.z + mci] + (int)tc[mri + a.w];
+                }
+                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)b.w;
+                const bool tb = t1 || (use_tabu && (int)tabu_ri[b.z & 0xFFFF] > t);
+                const bool ok = j > i;
+                mT = (ok && tb) ? min(mT, p) : mT;
+                mF = (ok && !tb) ? min(mF, p) : mF;
+            }
         }
-        const bool ok = act && j > i;
-        const bool tb = use_tabu && ((int)tabu[rj * c.M + mi] > t || (int)tabu[ri * c.M + mj] > t);
-        const bool blocked = tb && !(d < thr);
-        const uint32_t a = (uint32_t)min(mi, mj), bm = (uint32_t)max(mi, mj);
-        const uint32_t idx = c.R + a * M - (a * (a + 1u)) / 2u + (bm - a - 1u);
-        const uint64_t key = pack_key(blocked, d, idx);
-        if (DBG) {
-            if (ok) keys_out[idx] = key;
-        } else {
-            best = ok ? umin64(best, key) : best;
+        if (act) {
+            if (mF != 0xFFFFFFFFu) {
+                const int d = (int)(mF >> 6) - kPackBias;
+                const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
+                const uint32_t mj = c.seq[jw];
+                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                best = umin64(best, pack_key(false, d, swap_index(c.R, M, a, bm)));
+            }
+            if (mT != 0xFFFFFFFFu) {
+                const int d = (int)(mT >> 6) - kPackBias;
+                const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
+                const uint32_t mj = c.seq[jw];
+                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
+            }
         }
     }
     return best;
@@ -189,41 +247,78 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
 
 // Deal eval units round-robin over the TW wavefronts of the solve; gw is this
 // wavefront's rank.  Returns this lane's minimum key.
-template <typename TE, typename TB, bool DBG>
-__device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const TB *tabu, int chunk,
-                                             int gw, int TW, int lane, int t, int thr,
-                                             bool use_tabu, uint64_t *keys_out)
+template <typename TE, typename TB>
+__device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const TB *tabu, int gw,
+                                             int TW, int lane, int t, int thr, bool use_tabu)
 {
     uint64_t best = kKeyNone;
+    const int CH = c.chunk;
     const int nT = (c.M + kWave - 1) / kWave;
-    const int nRC = (c.NG + chunk - 1) / chunk;
+    const int nRC = (c.NG + CH - 1) / CH;
     int u = 0, mine = gw;
     for (int tl = 0; tl < nT; ++tl) {
+        const int jb = tl * kWave;
+        const int nSC = (c.M - jb + CH - 1) / CH;
+        const int nu = nRC + nSC;
+        if (mine >= u + nu) { u += nu; continue; }
+        const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
         for (int k = 0; k < nRC; ++k, ++u) {
             if (u != mine) continue;
             mine += TW;
-            const int G0 = k * chunk, G1 = min(c.NG, G0 + chunk);
-            best = umin64(best, relocate_unit<TE, TB, DBG>(c, tc, tabu, tl, G0, G1, lane, t, thr,
-                                                           use_tabu, keys_out));
+            const int G0 = k * CH, G1 = min(c.NG, G0 + CH);
+            best = umin64(best, relocate_unit<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
+                                                      use_tabu, rlo, rhi));
         }
-        const int jb = tl * kWave;
-        const int nSC = (c.M - jb + chunk - 1) / chunk;
         for (int k = 0; k < nSC; ++k, ++u) {
             if (u != mine) continue;
             mine += TW;
-            const int j0 = jb + k * chunk, j1 = min(c.M, j0 + chunk);
-            best = umin64(best, swap_unit<TE, TB, DBG>(c, tc, tabu, tl, j0, j1, lane, t, thr,
-                                                       use_tabu, keys_out));
+            const int j0 = jb + k * CH, j1 = min(c.M, j0 + CH);
+            best = umin64(best, swap_unit<TE, TB>(c, tc, tabu, tl, j0, j1, lane, t, thr, use_tabu));
         }
     }
     return best;
 }
 
 // ---------------------------------------------------------------------------
+// every slot's key, one move at a time (test hook; no segment tricks)
+// ---------------------------------------------------------------------------
+template <typename TE>
+__device__ void dump_keys(const Ctx &c, const TE *tc, const int32_t *tabu, int tid, int nthr, int t,
+                          int thr, bool use_tabu, uint64_t *keys)
+{
+    const int M = c.M;
+    for (int i = tid; i < M; i += nthr) {
+        const int4 pa = c.posA[i], pb = c.posB[i];
+        const int m = pb.z & 0xFFFF, ri = pb.z >> 16;
+        const int rem = pb.y - pb.x;
+        for (int G = 0; G < c.NG; ++G) {
+            const int4 g = c.gap[G];
+            const int d = rem + (int)tc[g.x + pa.y] + (int)tc[pa.x + g.y] - g.z;
+            const bool noop = (unsigned)(G - (i + ri)) < 2u;
+            const bool tb = use_tabu && tabu[g.w * M + m] > t;
+            keys[(uint32_t)m * c.NG + G] = noop ? kKeyNone : pack_key(tb && !(d < thr), d, (uint32_t)m * c.NG + G);
+        }
+        for (int j = i + 1; j < M; ++j) {
+            const int4 a = c.posA[j], b = c.posB[j];
+            const int mj = b.z & 0xFFFF, rj = b.z >> 16;
+            int d;
+            if (j == i + 1 && ri == rj)
+                d = (int)tc[pa.z + a.y] + (int)tc[a.x + pa.y] + (int)tc[pa.x + a.w]
+                  - ((int)tc[pa.z + pa.y] + (int)tc[pa.x + a.y] + (int)tc[a.x + a.w]);
+            else
+                d = (int)tc[pa.z + a.y] + (int)tc[a.x + pa.w] + (int)tc[a.z + pa.y] + (int)tc[pa.x + a.w]
+                  - pb.x - b.x;
+            const bool tb = use_tabu && (tabu[rj * M + m] > t || tabu[ri * M + mj] > t);
+            const uint32_t idx = swap_index(c.R, (uint32_t)M, (uint32_t)min(m, mj), (uint32_t)max(m, mj));
+            keys[idx] = pack_key(tb && !(d < thr), d, idx);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS setup
 // ---------------------------------------------------------------------------
-template <typename TE, typename TB>
-__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V)
+__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V, int chunk)
 {
     Ctx c;
     c.mrow = (int32_t *)(smem + ly.mrow);
@@ -235,25 +330,28 @@ __device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V)
     c.rt = (uint16_t *)(smem + ly.rt);
     c.rof = (uint16_t *)(smem + ly.rof);
     c.pof = (uint16_t *)(smem + ly.pof);
-    c.xr = (int32_t *)(smem + ly.xr);
-    c.yc = (int32_t *)(smem + ly.yc);
-    c.outv = (int32_t *)(smem + ly.outv);
-    c.link = (int32_t *)(smem + ly.link);
-    c.ga = (int32_t *)(smem + ly.ga);
-    c.gb = (int32_t *)(smem + ly.gb);
-    c.gc = (int32_t *)(smem + ly.gc);
-    c.gr = (uint16_t *)(smem + ly.gr);
+    c.posA = (int4 *)(smem + ly.posA);
+    c.posB = (int4 *)(smem + ly.posB);
+    c.gap = (int4 *)(smem + ly.gap);
+    c.prank = (uint8_t *)(smem + ly.prank);
     c.red = (uint64_t *)(smem + ly.red);
     c.M = M;
     c.V = V;
     c.NG = M + V;
+    c.chunk = chunk;
     c.R = (uint32_t)M * (uint32_t)(M + V);
     return c;
 }
 
-__device__ __forceinline__ void copy_words(uint32_t *dst, const uint32_t *src, int n, int tid, int nthr)
+template <typename TE>
+__device__ __forceinline__ void load_instance(const InstDev &I, const Ctx &c, TE *tc, int tid, int nthr)
 {
-    for (int k = tid; k < n; k += nthr) dst[k] = src[k];
+    const int words = (int)(((int64_t)I.R * I.Cs * (int64_t)sizeof(TE)) / 4);
+    const uint32_t *src = (const uint32_t *)I.tc;
+    uint32_t *dst = (uint32_t *)tc;
+    for (int k = tid; k < words; k += nthr) dst[k] = src[k];
+    for (int k = tid; k < c.M; k += nthr) { c.mrow[k] = I.mrow[k]; c.mcol[k] = I.mcol[k]; }
+    for (int k = tid; k < c.V; k += nthr) { c.vrow[k] = I.vrow[k]; c.vcol[k] = I.vcol[k]; }
 }
 
 // route-of-position, position-of-mission and vehicle-of-mission from seq/off
@@ -276,12 +374,10 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
                           int nthr)
 {
     const int M = c.M, V = c.V;
-    int32_t *pi = c.link;      // mission order
-    int32_t *draw = c.xr;      // j of each Fisher-Yates step
-    int32_t *lastx = c.ga;     // exit row offset at the end of each route
-    int32_t *cnt = c.gb;       // missions per vehicle
-    int32_t *veh = c.outv;     // vehicle chosen at each step
-    int32_t *cur = c.gc;       // placement cursor per vehicle
+    int32_t *scr = (int32_t *)c.posA;      // 4M ints
+    int32_t *pi = scr, *draw = scr + M, *veh = scr + 2 * M;
+    int32_t *scv = (int32_t *)c.gap;       // 4(M+V) ints
+    int32_t *lastx = scv, *cnt = scv + V, *curv = scv + 2 * V;
     for (int i = tid; i < M; i += nthr) {
         pi[i] = i;
         if (i >= 1) draw[i] = (int32_t)(splitmix_at(seed, (uint64_t)(M - i)) % (uint64_t)(i + 1));
@@ -313,21 +409,21 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
             if ((vs & (kWave - 1)) == lane) { lastx[vs] = mr; cnt[vs] += 1; }
             if (lane == 0) veh[s] = vs;
         }
-        if (lane == 0) c.red[40] = (uint64_t)acc;
+        if (lane == 0) c.red[100] = (uint64_t)acc;
     }
     __syncthreads();
     if (tid == 0) {
         int o = 0;
-        for (int v = 0; v < V; ++v) { c.off[v] = o; cur[v] = o; o += cnt[v]; }
+        for (int v = 0; v < V; ++v) { c.off[v] = o; curv[v] = o; o += cnt[v]; }
         c.off[V] = o;
         for (int s = 0; s < M; ++s) {
             const int v = veh[s];
-            c.seq[cur[v]++] = (uint16_t)pi[s];
+            c.seq[curv[v]++] = (uint16_t)pi[s];
         }
     }
     __syncthreads();
     index_routes(c, tid, nthr);
-    const int64_t acc = (int64_t)c.red[40];
+    const int64_t acc = (int64_t)c.red[100];
     __syncthreads();
     return acc + svc_sum;
 }
@@ -354,16 +450,12 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), (int)sizeof(TB));
-    Ctx c = make_ctx<TE, TB>(smem, ly, M, V);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk);
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
 
-    copy_words((uint32_t *)tc, (const uint32_t *)I.tc, (int)(((int64_t)I.R * I.Cs * sizeof(TE)) / 4), tid, nthr);
-    copy_words((uint32_t *)c.mrow, (const uint32_t *)I.mrow, M, tid, nthr);
-    copy_words((uint32_t *)c.mcol, (const uint32_t *)I.mcol, M, tid, nthr);
-    copy_words((uint32_t *)c.vrow, (const uint32_t *)I.vrow, V, tid, nthr);
-    copy_words((uint32_t *)c.vcol, (const uint32_t *)I.vcol, V, tid, nthr);
+    load_instance<TE>(I, c, tc, tid, nthr);
     __syncthreads();
 
     int64_t cur, best;
@@ -402,7 +494,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_all<TE, TB, false>(c, tc, tabu, J.chunk, gw, TW, lane, t, thr, use_tabu, nullptr);
+        uint64_t k = eval_all<TE, TB>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) c.red[wave] = k;
         __syncthreads();
@@ -452,11 +544,11 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (!use_tabu && d >= 0) { stopped = 1; break; }
         const int tval = t + J.tenure + 1;
         bool was_tabu;
-        bool is_swap = idx >= c.R;
+        const bool is_swap = idx >= c.R;
         if (!is_swap) {
             const int m = (int)(idx / (uint32_t)c.NG);
             const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
-            const int v = c.gr[G];
+            const int v = c.gap[G].w;
             const int g = G - c.off[v] - v;
             const int s = c.pof[m];
             const int rs = c.rt[s];
@@ -465,7 +557,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
             was_tabu = use_tabu && (int)tabu[v * M + m] > t;
             const int lo = min(s, q), hi = max(s, q);
             __syncthreads();
-            int32_t *tmp = c.xr;
+            int32_t *tmp = (int32_t *)c.posB;
             for (int kk = lo + tid; kk <= hi; kk += nthr)
                 tmp[kk] = (kk == q) ? m : (q >= s ? c.seq[kk + 1] : c.seq[kk - 1]);
             if (v > rs) for (int r = rs + 1 + tid; r <= v; r += nthr) c.off[r] -= 1;
@@ -544,6 +636,260 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     }
 }
 
+// ---------------------------------------------------------------------------
+// global schedule: state in HBM, gridDim.x workgroups per solve, three grid
+// barriers per iteration (after prep, the argmin exchange, after apply)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool grid_barrier(Xchg *xs, int nwg, uint32_t &nb, uint64_t *flag)
+{
+    __syncthreads();
+    ++nb;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(&xs->cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = nb * (uint32_t)nwg;
+        uint32_t spins = 0, ab = 0;
+        while (__hip_atomic_load(&xs->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            ab = __hip_atomic_load(&xs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ab) break;
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(&xs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *flag = ab;
+    }
+    __syncthreads();
+    return *flag == 0;
+}
+
+__device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B, int p,
+                                          uint64_t *red, int chunk)
+{
+    Ctx c;
+    c.mrow = I.mrow;
+    c.mcol = I.mcol;
+    c.vrow = I.vrow;
+    c.vcol = I.vcol;
+    c.off = B.off[p];
+    c.seq = B.seq[p];
+    c.rt = B.rt[p];
+    c.rof = B.rof[p];
+    c.pof = B.pof[p];
+    c.posA = B.posA;
+    c.posB = B.posB;
+    c.gap = B.gap;
+    c.prank = B.prank;
+    c.red = red;
+    c.M = I.M;
+    c.V = I.V;
+    c.NG = I.M + I.V;
+    c.chunk = chunk;
+    c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
+    return c;
+}
+
+template <typename TE, typename TB>
+__device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, uint64_t *red)
+{
+    const InstDev &I = *J.inst;
+    GlobalBufs &B = *J.gb;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
+    const int gtid = wg * nthr + tid, gthr = nwg * nthr;
+    const int M = I.M, V = I.V;
+    const TE *tc = (const TE *)I.tc;
+    TB *tabu = (TB *)B.tabu;
+    const bool writer = wg == 0;
+    SolveState *st = J.st;
+    uint32_t nb = 0;
+    uint64_t *flag = red + 66;
+
+    int p, best_iter, stopped;
+    int64_t cur, best;
+    bool aborted = false, pending = false;
+    if (J.resume && st && st->valid) {
+        p = B.cur;
+        cur = st->cur;
+        best = st->best;
+        best_iter = st->best_iter;
+        stopped = st->stopped;
+    } else {
+        p = 0;
+        if (wg == 0) {
+            const Ctx c0 = global_ctx(I, B, 0, red, J.chunk);
+            const int64_t g = greedy<TE>(c0, tc, J.seed, I.svc_sum, tid, nthr);
+            if (tid == 0) xs->init_obj = g;
+            snapshot(c0, J, tid, nthr);
+        }
+        for (int k = gtid; k < M * V; k += gthr) tabu[k] = (TB)0;
+        if (!grid_barrier(xs, nwg, nb, flag)) aborted = true;
+        cur = xs->init_obj;
+        best = cur;
+        best_iter = -1;
+        stopped = 0;
+    }
+
+    const bool use_tabu = J.variant == AT_TABU;
+    const int gw = wg * nwaves + wave, TW = nwaves * nwg;
+    int t = J.t_begin;
+    for (; !aborted && t < J.t_end && !stopped; ++t) {
+        const Ctx c = global_ctx(I, B, p, red, J.chunk);
+        prep<TE>(c, tc, gtid, gthr);
+        if (pending && writer) snapshot(c, J, tid, nthr);
+        pending = false;
+        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
+        int thr = INT32_MIN;
+        if (J.aspiration) {
+            const int64_t g = best - cur;
+            thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
+        }
+        uint64_t k = eval_all<TE, TB>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
+        k = wave_min(k);
+        if (lane == 0) red[wave] = k;
+        __syncthreads();
+        if (tid < kWave) {
+            uint64_t w = lane < nwaves ? red[lane] : kKeyNone;
+            w = wave_min(w);
+            if (lane == 0) __hip_atomic_fetch_min(&xs->key[t % 3], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
+        const uint64_t key = __hip_atomic_load(&xs->key[t % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (writer && tid == 0)
+            __hip_atomic_store(&xs->key[(t + 2) % 3], kKeyNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (key == kKeyNone) {
+            if (!use_tabu) { stopped = 1; break; }
+            if (writer && tid == 0 && J.trace) {
+                J.tr_move[t] = 0xFFFFFFFFu; J.tr_delta[t] = 0; J.tr_obj[t] = cur; J.tr_flags[t] = 0;
+            }
+            // routes unchanged: copy them to the other buffer
+            const Ctx n = global_ctx(I, B, p ^ 1, red, J.chunk);
+            for (int kk = gtid; kk < M; kk += gthr) {
+                n.seq[kk] = c.seq[kk]; n.rt[kk] = c.rt[kk];
+                n.pof[kk] = c.pof[kk]; n.rof[kk] = c.rof[kk];
+            }
+            for (int r = gtid; r <= V; r += gthr) n.off[r] = c.off[r];
+            if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
+            p ^= 1;
+            continue;
+        }
+        const bool blocked = (key >> 63) != 0;
+        const int d = (int)((uint32_t)(key >> 32) & 0x7FFFFFFFu) - kDeltaBias;
+        const uint32_t idx = (uint32_t)key;
+        if (!use_tabu && d >= 0) { stopped = 1; break; }
+        const int tval = t + J.tenure + 1;
+        const bool is_swap = idx >= c.R;
+        const Ctx n = global_ctx(I, B, p ^ 1, red, J.chunk);
+        bool was_tabu;
+        if (!is_swap) {
+            const int m = (int)(idx / (uint32_t)c.NG);
+            const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
+            const int v = c.gap[G].w;
+            const int g = G - c.off[v] - v;
+            const int s = c.pof[m];
+            const int rs = c.rt[s];
+            const int fp = c.off[v] + g;
+            const int q = fp - (fp > s ? 1 : 0);
+            was_tabu = use_tabu && (int)tabu[v * M + m] > t;
+            const int lo = min(s, q), hi = max(s, q);
+            auto offn = [&](int r) {
+                int o = c.off[r];
+                if (v > rs && r > rs && r <= v) o -= 1;
+                if (v < rs && r > v && r <= rs) o += 1;
+                return o;
+            };
+            for (int kk = gtid; kk < M; kk += gthr) {
+                int mm, r;
+                if (kk >= lo && kk <= hi) {
+                    mm = (kk == q) ? m : (q >= s ? c.seq[kk + 1] : c.seq[kk - 1]);
+                    int a = 0, b = V - 1;
+                    while (a < b) {
+                        const int mid = (a + b + 1) >> 1;
+                        if (offn(mid) <= kk) a = mid; else b = mid - 1;
+                    }
+                    r = a;
+                } else {
+                    mm = c.seq[kk];
+                    r = c.rt[kk];
+                }
+                n.seq[kk] = (uint16_t)mm;
+                n.rt[kk] = (uint16_t)r;
+                n.pof[mm] = (uint16_t)kk;
+                n.rof[mm] = (uint16_t)r;
+            }
+            for (int r = gtid; r <= V; r += gthr) n.off[r] = offn(r);
+            if (writer && tid == 0 && use_tabu) tabu[rs * M + m] = (TB)tval;
+        } else {
+            const uint32_t sp = idx - c.R;
+            const double A = 2.0 * (double)M - 1.0;
+            int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
+            a = max(0, min(a, M - 2));
+            auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
+            while (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
+            while (a > 0 && rowstart(a) > (int64_t)sp) --a;
+            const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
+            const int s1 = c.pof[m1], s2 = c.pof[m2];
+            const int r1 = c.rt[s1], r2 = c.rt[s2];
+            was_tabu = use_tabu && ((int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t);
+            for (int kk = gtid; kk < M; kk += gthr) {
+                const int mm = kk == s1 ? m2 : (kk == s2 ? m1 : (int)c.seq[kk]);
+                const int r = c.rt[kk];
+                n.seq[kk] = (uint16_t)mm;
+                n.rt[kk] = (uint16_t)r;
+                n.pof[mm] = (uint16_t)kk;
+                n.rof[mm] = (uint16_t)r;
+            }
+            for (int r = gtid; r <= V; r += gthr) n.off[r] = c.off[r];
+            if (writer && tid == 0 && use_tabu) {
+                tabu[r1 * M + m1] = (TB)tval;
+                tabu[r2 * M + m2] = (TB)tval;
+            }
+        }
+        cur += d;
+        if (writer && tid == 0 && J.trace) {
+            J.tr_move[t] = idx;
+            J.tr_delta[t] = d;
+            J.tr_obj[t] = cur;
+            J.tr_flags[t] = (uint8_t)((is_swap ? 1 : 0) | ((was_tabu && !blocked) ? 2 : 0) | (blocked ? 4 : 0));
+        }
+        if (cur < best) {
+            best = cur;
+            best_iter = t;
+            pending = true;
+        }
+        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
+        p ^= 1;
+    }
+    if (!writer) return;
+    if (pending && !aborted) snapshot(global_ctx(I, B, p, red, J.chunk), J, tid, nthr);
+    if (tid == 0) {
+        J.scal->best_obj = best;
+        J.scal->final_obj = cur;
+        J.scal->iters_done = t;
+        J.scal->best_iter = best_iter;
+        J.scal->stopped = stopped;
+        J.scal->status = aborted ? AT_EDEVICE : AT_OK;
+        B.cur = p;
+        if (J.save && st) {
+            st->cur = cur;
+            st->best = best;
+            st->t = t;
+            st->best_iter = best_iter;
+            st->stopped = stopped;
+            st->valid = 1;
+        }
+    }
+}
+
+template <typename TE, typename TB>
+__global__ void __launch_bounds__(1024) k_search_global(const JobDev *job, Xchg *xs)
+{
+    __shared__ uint64_t red[128];
+    run_job_global<TE, TB>(*job, (int)blockIdx.x, (int)gridDim.x, xs, red);
+}
+
 // One workgroup per job; jobs are taken from an atomic queue until exhausted.
 template <typename TE, typename TB>
 __global__ void __launch_bounds__(1024) k_search_wg(const JobDev *jobs, int n_jobs, Xchg *xs)
@@ -569,7 +915,8 @@ __global__ void __launch_bounds__(1024) k_search_multi(const JobDev *job, Xchg *
     run_job<TE, TB, true>(*job, smem, (int)blockIdx.x, (int)gridDim.x, xs);
 }
 
-// every slot's key for a given state (test hook)
+// Test hook: every slot's key for a given state (keys[0..n_slots)), and the
+// minimum the search's own eval finds for that state (keys[n_slots]).
 template <typename TE>
 __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int32_t *off,
                                                      const int32_t *seq, const int32_t *tabu_until,
@@ -583,14 +930,10 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), 4);
-    Ctx c = make_ctx<TE, int32_t>(smem, ly, M, V);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk);
     TE *tc = (TE *)(smem + ly.tc);
     int32_t *tabu = (int32_t *)(smem + ly.tabu);
-    copy_words((uint32_t *)tc, (const uint32_t *)I.tc, (int)(((int64_t)I.R * I.Cs * sizeof(TE)) / 4), tid, nthr);
-    copy_words((uint32_t *)c.mrow, (const uint32_t *)I.mrow, M, tid, nthr);
-    copy_words((uint32_t *)c.mcol, (const uint32_t *)I.mcol, M, tid, nthr);
-    copy_words((uint32_t *)c.vrow, (const uint32_t *)I.vrow, V, tid, nthr);
-    copy_words((uint32_t *)c.vcol, (const uint32_t *)I.vcol, V, tid, nthr);
+    load_instance<TE>(I, c, tc, tid, nthr);
     for (int i = tid; i < M; i += nthr) c.seq[i] = (uint16_t)seq[i];
     for (int v = tid; v <= V; v += nthr) c.off[v] = off[v];
     // external entry m*V + v holds the last blocked iteration; internal [v][m] holds it + 1
@@ -608,8 +951,17 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
         const int64_t g = best - cur;
         thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
     }
-    eval_all<TE, int32_t, true>(c, tc, tabu, J.chunk, wave, nwaves, lane, t, thr,
-                                J.variant == AT_TABU, keys);
+    const bool use_tabu = J.variant == AT_TABU;
+    dump_keys<TE>(c, tc, tabu, tid, nthr, t, thr, use_tabu, keys);
+    uint64_t k = eval_all<TE, int32_t>(c, tc, tabu, wave, nwaves, lane, t, thr, use_tabu);
+    k = wave_min(k);
+    if (lane == 0) c.red[wave] = k;
+    __syncthreads();
+    if (tid < kWave) {
+        uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
+        w = wave_min(w);
+        if (lane == 0) keys[n_slots(M, V)] = w;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -658,6 +1010,40 @@ hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int bl
     if (esz16) return coop_launch<uint16_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
     if (tb16) return coop_launch<int32_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
     return coop_launch<int32_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
+}
+
+template <typename TE, typename TB>
+static hipError_t coop_launch_global(const JobDev *job, Xchg *xs, int n_groups, int block, hipStream_t s)
+{
+    void *args[] = {(void *)&job, (void *)&xs};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search_global<TE, TB>),
+                                      dim3(n_groups), dim3(block), args, 0, s);
+}
+
+hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block, int tb16,
+                                int esz16, hipStream_t s)
+{
+    if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(job, xs, n_groups, block, s);
+    if (esz16) return coop_launch_global<uint16_t, int32_t>(job, xs, n_groups, block, s);
+    if (tb16) return coop_launch_global<int32_t, uint16_t>(job, xs, n_groups, block, s);
+    return coop_launch_global<int32_t, int32_t>(job, xs, n_groups, block, s);
+}
+
+template <typename TE, typename TB>
+static int occupancy_global(int block)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_global<TE, TB>, block, 0) != hipSuccess)
+        return 0;
+    return per_cu * num_cus();
+}
+
+int max_groups_global(int block, int tb16, int esz16)
+{
+    if (esz16 && tb16) return occupancy_global<uint16_t, uint16_t>(block);
+    if (esz16) return occupancy_global<uint16_t, int32_t>(block);
+    if (tb16) return occupancy_global<int32_t, uint16_t>(block);
+    return occupancy_global<int32_t, int32_t>(block);
 }
 
 template <typename TE, typename TB>

@@ -1,0 +1,370 @@
+// server.hip -- continuous-batching serving loop (at_server_* in atabu.h).
+//
+// The server owns one device arena of `hbm_budget_bytes`.  A submitted request
+// waits in a FIFO until a slot and enough arena memory are free; it is then
+// admitted: its instance is prepared into the arena (checks + compact travel
+// block), and it joins the resident solves.  Every at_server_progress call
+// that finds the device idle retires finished solves, admits waiting
+// requests, and launches the next chunk: every resident solve advances
+// `chunk_iters` iterations from its saved state (routes, tabu table,
+// iteration, objectives), so a request that arrives while others run starts
+// at the next chunk boundary and shares the GPU with them.  Because every
+// solve is deterministic and resumes exactly where it stopped, its result does
+// not depend on what else is resident or on the chunking.
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "atabu.h"
+#include "atabu_internal.h"
+#include "engine.h"
+
+namespace at {
+
+namespace {
+
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes, coalesced
+
+    void init(char *b, size_t n) { base = b; size = n; free_.clear(); free_[0] = n; }
+
+    char *alloc(size_t n)
+    {
+        n = al256(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, left = it->second - n;
+            free_.erase(it);
+            if (left) free_[off + n] = left;
+            return base + off;
+        }
+        return nullptr;
+    }
+
+    void release(char *p, size_t n)
+    {
+        n = al256(n);
+        size_t off = (size_t)(p - base);
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) { n += next->second; next = free_.erase(next); }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) { prev->second += n; return; }
+        }
+        free_[off] = n;
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    at_instance inst{};
+    at_params pr{};
+    size_t bytes = 0;
+    char *mem = nullptr;
+    // carved from mem
+    InstDev *dinst = nullptr;
+    JobScal *scal = nullptr;
+    SolveState *st = nullptr;
+    at_result out{};                  // device arrays in mem
+    InstDev host_inst{};
+    JobHost job;
+    int t = 0;
+    bool admitted = false, done = false;
+    JobScal last{};
+};
+
+size_t request_bytes(const at_instance &in, const at_params &pr)
+{
+    const size_t M = (size_t)in.n_missions, V = (size_t)in.n_vehicles;
+    size_t b = al256(sizeof(InstDev)) + al256(sizeof(JobScal)) + al256(sizeof(SolveState));
+    b += inst_bytes(in);
+    b += al256(4 * M) + al256(4 * (V + 1)) + al256(4 * M * V);          // saved routes + tabu
+    b += al256(4 * (V + 1)) + 2 * al256(4 * (M ? M : 1));                // best routes
+    if (pr.trace) {
+        const size_t n = (size_t)(pr.max_iters > 0 ? pr.max_iters : 1);
+        b += al256(4 * n) * 2 + al256(8 * n) + al256(n);
+    }
+    if (may_need_global(in, pr)) b += gstate_bytes(in, pr);
+    return b;
+}
+
+}  // namespace
+
+struct Server {
+    hipStream_t s = nullptr;
+    char *dev = nullptr;
+    size_t budget = 0;
+    int max_slots = 0, chunk = 0;
+    Arena arena;
+    JobDev *djobs = nullptr;
+    Xchg *xs = nullptr;
+    hipEvent_t done_ev = nullptr;
+    bool in_flight = false;
+    uint64_t next_ticket = 1;
+    std::deque<Request *> waiting;
+    std::vector<Request *> active;
+    std::map<uint64_t, Request *> all;
+    std::vector<JobDev> table;        // host copy of the last launch's job table
+
+    ~Server()
+    {
+        if (in_flight && done_ev) (void)hipEventSynchronize(done_ev);
+        for (auto &kv : all) delete kv.second;
+        if (done_ev) (void)hipEventDestroy(done_ev);
+        if (dev) (void)hipFree(dev);
+    }
+
+    // Lay out a request's arena block; returns the saved-state table to upload.
+    SolveState carve(Request &r)
+    {
+        char *p = r.mem;
+        const size_t M = (size_t)r.inst.n_missions, V = (size_t)r.inst.n_vehicles;
+        r.dinst = (InstDev *)p; p += al256(sizeof(InstDev));
+        r.scal = (JobScal *)p; p += al256(sizeof(JobScal));
+        r.st = (SolveState *)p; p += al256(sizeof(SolveState));
+        carve_inst(r.host_inst, r.inst, p); p += inst_bytes(r.inst);
+        SolveState st{};
+        st.seq = (int32_t *)p; p += al256(4 * M);
+        st.off = (int32_t *)p; p += al256(4 * (V + 1));
+        st.tabu = (int32_t *)p; p += al256(4 * M * V);
+        r.out.route_off = (int32_t *)p; p += al256(4 * (V + 1));
+        r.out.route_seq = (int32_t *)p; p += al256(4 * (M ? M : 1));
+        r.out.route_of = (int32_t *)p; p += al256(4 * (M ? M : 1));
+        if (r.pr.trace) {
+            const size_t n = (size_t)(r.pr.max_iters > 0 ? r.pr.max_iters : 1);
+            r.out.tr_move = (uint32_t *)p; p += al256(4 * n);
+            r.out.tr_delta = (int32_t *)p; p += al256(4 * n);
+            r.out.tr_obj = (int64_t *)p; p += al256(8 * n);
+            r.out.tr_flags = (uint8_t *)p; p += al256(n);
+        }
+        r.job.gstate = may_need_global(r.inst, r.pr) ? (GlobalBufs *)p : nullptr;
+        r.job.out = r.out;
+        return st;
+    }
+
+    int admit(Request &r)
+    {
+        const SolveState st = carve(r);
+        // state table: pointers, valid = 0 (the first chunk starts from the greedy solution);
+        // prepare_instances below synchronises the stream before `st` goes out of scope
+        hipError_t e = hipMemcpyAsync(r.st, &st, sizeof(SolveState), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "server: state upload");
+        std::vector<InstDev> ih(1, r.host_inst);
+        int rc = prepare_instances(1, r.dinst, ih, s);
+        if (rc) return rc;
+        r.host_inst = ih[0];
+        r.job.inst = 0;
+        r.job.pr = r.pr;
+        r.job.pr.schedule = r.pr.schedule == AT_SCHED_MULTI ? AT_SCHED_AUTO : r.pr.schedule;
+        r.job.seed = r.pr.restart_seed;
+        rc = plan_job(r.job, r.host_inst, false);
+        if (rc) return rc;
+        if (r.job.kind == AT_SCHED_GLOBAL) {
+            std::vector<JobHost> one(1, r.job);
+            rc = upload_gstates(one, ih, s);
+            if (rc) return rc;
+        }
+        r.admitted = true;
+        r.t = 0;
+        return AT_OK;
+    }
+
+    // Retire finished solves after the last launch completed.
+    int collect()
+    {
+        if (active.empty()) return AT_OK;
+        std::vector<JobScal> hs(active.size());
+        for (size_t k = 0; k < active.size(); ++k) {
+            hipError_t e = hipMemcpyAsync(&hs[k], active[k]->scal, sizeof(JobScal), hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return hip_fail(e, "server: read back");
+        }
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "server: chunk");
+        std::vector<Request *> keep;
+        for (size_t k = 0; k < active.size(); ++k) {
+            Request *r = active[k];
+            r->last = hs[k];
+            r->t = hs[k].iters_done;
+            if (hs[k].status != AT_OK || hs[k].stopped || r->t >= r->pr.max_iters) r->done = true;
+            else keep.push_back(r);
+        }
+        active.swap(keep);
+        return AT_OK;
+    }
+
+    int launch()
+    {
+        if (active.empty()) return AT_OK;
+        std::vector<JobHost> jobs;
+        std::vector<InstDev> ih;
+        jobs.reserve(active.size());
+        for (size_t k = 0; k < active.size(); ++k) {
+            JobHost h = active[k]->job;
+            h.inst = (int)k;
+            jobs.push_back(h);
+            ih.push_back(active[k]->host_inst);
+        }
+        const std::vector<int> order = order_jobs(jobs);
+        std::vector<JobDev> hj(jobs.size());
+        for (size_t k = 0; k < order.size(); ++k) {
+            Request *r = active[(size_t)order[k]];
+            int rc = fill_job(hj[k], jobs[(size_t)order[k]], r->dinst, r->scal);
+            if (rc) return rc;
+            hj[k].t_begin = r->t;
+            hj[k].t_end = std::min(r->pr.max_iters, r->t + chunk);
+            hj[k].resume = 1;
+            hj[k].save = 1;
+            hj[k].st = r->st;
+        }
+        // the host copy of the table stays alive until the launch has completed
+        table.swap(hj);
+        hipError_t e = hipMemcpyAsync(djobs, table.data(), sizeof(JobDev) * table.size(),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "server: job upload");
+        int rc = launch_jobs(jobs, order, djobs, xs, s);
+        if (rc) return rc;
+        if ((e = hipEventRecord(done_ev, s)) != hipSuccess) return hip_fail(e, "server: event");
+        in_flight = true;
+        return AT_OK;
+    }
+};
+
+}  // namespace at
+
+using namespace at;
+
+extern "C" {
+
+int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_iters, void *stream,
+                     void **server)
+{
+    if (!server) return fail(AT_EINVAL, "null server handle");
+    if (max_slots < 1 || max_slots > 65536) return fail(AT_EINVAL, "max_slots outside [1, 65536]");
+    if (chunk_iters < 1) return fail(AT_EINVAL, "chunk_iters must be positive");
+    const size_t fixed = al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots);
+    if (hbm_budget_bytes < fixed + (1 << 20)) return fail(AT_ENOMEM, "budget too small");
+    Server *sv = new Server();
+    sv->s = (hipStream_t)stream;
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    sv->chunk = chunk_iters;
+    hipError_t e = hipMalloc((void **)&sv->dev, hbm_budget_bytes);
+    if (e != hipSuccess) { delete sv; return hip_fail(e, "server arena"); }
+    sv->xs = (Xchg *)sv->dev;
+    sv->djobs = (JobDev *)(sv->dev + al256(sizeof(Xchg)));
+    sv->arena.init(sv->dev + fixed, hbm_budget_bytes - fixed);
+    if ((e = hipEventCreateWithFlags(&sv->done_ev, hipEventDisableTiming)) != hipSuccess) {
+        delete sv;
+        return hip_fail(e, "server event");
+    }
+    *server = sv;
+    return AT_OK;
+}
+
+int at_server_submit(void *server, const at_instance *inst, const at_params *params, uint64_t *ticket)
+{
+    Server *sv = (Server *)server;
+    if (!sv || !ticket) return fail(AT_EINVAL, "null argument");
+    int rc = check_scalars(inst, params);
+    if (rc) return rc;
+    Request *r = new Request();
+    r->inst = *inst;
+    r->pr = *params;
+    r->bytes = request_bytes(*inst, *params);
+    if (r->bytes > sv->arena.size) {
+        delete r;
+        return fail(AT_ENOMEM, "request needs %zu bytes, the server budget holds %zu", r->bytes, sv->arena.size);
+    }
+    r->ticket = sv->next_ticket++;
+    sv->waiting.push_back(r);
+    sv->all[r->ticket] = r;
+    *ticket = r->ticket;
+    return AT_OK;
+}
+
+int at_server_progress(void *server, int32_t *n_active)
+{
+    Server *sv = (Server *)server;
+    if (!sv) return fail(AT_EINVAL, "null server");
+    if (sv->in_flight) {
+        hipError_t q = hipEventQuery(sv->done_ev);
+        if (q == hipErrorNotReady) {
+            if (n_active) *n_active = (int32_t)sv->active.size();
+            return AT_OK;
+        }
+        if (q != hipSuccess) return hip_fail(q, "server: chunk");
+        sv->in_flight = false;
+        int rc = sv->collect();
+        if (rc) return rc;
+    }
+    // admit in arrival order while a slot and memory are free
+    while (!sv->waiting.empty() && (int)sv->active.size() < sv->max_slots) {
+        Request *r = sv->waiting.front();
+        r->mem = sv->arena.alloc(r->bytes);
+        if (!r->mem) break;
+        sv->waiting.pop_front();
+        int rc = sv->admit(*r);
+        if (rc) {
+            r->done = true;
+            r->last.status = rc;
+            sv->arena.release(r->mem, r->bytes);
+            r->mem = nullptr;
+            continue;
+        }
+        sv->active.push_back(r);
+    }
+    int rc = sv->launch();
+    if (n_active) *n_active = (int32_t)(sv->active.size() + sv->waiting.size());
+    return rc;
+}
+
+int at_server_poll(void *server, uint64_t ticket, at_result *out)
+{
+    Server *sv = (Server *)server;
+    if (!sv || !out) return fail(AT_EINVAL, "null argument");
+    auto it = sv->all.find(ticket);
+    if (it == sv->all.end()) return fail(AT_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    if (!r->done) return AT_EAGAIN;
+    hipError_t e = hipSuccess;
+    if (r->mem && r->last.status == AT_OK) {
+        const size_t M = (size_t)r->inst.n_missions, V = (size_t)r->inst.n_vehicles;
+        if (out->route_off) e = hipMemcpyAsync(out->route_off, r->out.route_off, 4 * (V + 1), hipMemcpyDeviceToDevice, sv->s);
+        if (e == hipSuccess && out->route_seq && M) e = hipMemcpyAsync(out->route_seq, r->out.route_seq, 4 * M, hipMemcpyDeviceToDevice, sv->s);
+        if (e == hipSuccess && out->route_of && M) e = hipMemcpyAsync(out->route_of, r->out.route_of, 4 * M, hipMemcpyDeviceToDevice, sv->s);
+        const size_t n = (size_t)r->last.iters_done;
+        if (e == hipSuccess && r->pr.trace && n) {
+            if (out->tr_move) e = hipMemcpyAsync(out->tr_move, r->out.tr_move, 4 * n, hipMemcpyDeviceToDevice, sv->s);
+            if (e == hipSuccess && out->tr_delta) e = hipMemcpyAsync(out->tr_delta, r->out.tr_delta, 4 * n, hipMemcpyDeviceToDevice, sv->s);
+            if (e == hipSuccess && out->tr_obj) e = hipMemcpyAsync(out->tr_obj, r->out.tr_obj, 8 * n, hipMemcpyDeviceToDevice, sv->s);
+            if (e == hipSuccess && out->tr_flags) e = hipMemcpyAsync(out->tr_flags, r->out.tr_flags, n, hipMemcpyDeviceToDevice, sv->s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->s);
+    }
+    out->best_obj = r->last.best_obj;
+    out->final_obj = r->last.final_obj;
+    out->iters_done = r->last.iters_done;
+    out->best_iter = r->last.best_iter;
+    out->status = r->last.status;
+    out->search_ms = 0.f;
+    const int status = r->last.status;
+    if (r->mem) sv->arena.release(r->mem, r->bytes);
+    sv->all.erase(it);
+    delete r;
+    if (e != hipSuccess) return hip_fail(e, "server: result copy");
+    return status == AT_OK ? AT_OK : fail(status, "request failed with status %d", status);
+}
+
+int at_server_destroy(void *server)
+{
+    Server *sv = (Server *)server;
+    if (!sv) return fail(AT_EINVAL, "null server");
+    delete sv;
+    return AT_OK;
+}
+
+}  // extern "C"

@@ -65,9 +65,10 @@ def test_every_slot_key(shape, chunk):
         for best in (cur, cur - 50):
             for t in (0, 6, 9):
                 want = P.keys(off, seq, tabu, t, cur, best)
-                got = at.debug_eval_moves(dev, off, seq, tabu, t, cur, best, chunk=chunk)
+                got, fast = at.debug_eval_moves(dev, off, seq, tabu, t, cur, best, chunk=chunk)
                 bad = np.nonzero(got != want)[0]
                 assert bad.size == 0, (shape, k, t, best - cur, bad[:5], got[bad[:5]], want[bad[:5]])
+                assert fast == int(want.min()), (shape, k, t, best - cur, hex(fast), hex(int(want.min())))
 
 
 # ------------------------------------------------------------------ whole trajectories
@@ -198,3 +199,39 @@ def test_determinism_repeated():
     for groups in (2, 5):
         g = at.solve(dev, tenure=9, iters=400, schedule=2, n_groups=groups)
         assert np.array_equal(g["tr_move"].cpu().numpy(), tm), groups
+
+
+# ------------------------------------------------------------------ HBM-resident schedule
+
+@pytest.mark.parametrize("groups", [1, 4, 16])
+def test_m400_global_schedule(groups):
+    inst = m400_instance(0)
+    _, o = _m400_oracle(0)
+    g = at.solve(_dev(inst), tenure=15, iters=5000, schedule=at.SCHED_GLOBAL, n_groups=groups)
+    assert_same_result(o, g, f"16x400 tabu global/{groups}")
+
+
+def test_m400_global_schedule_ns():
+    inst = m400_instance(0)
+    _, o = _m400_oracle(1)
+    g = at.solve(_dev(inst), variant=at.AT_NS, tenure=15, iters=5000, schedule=at.SCHED_GLOBAL,
+                 n_groups=8)
+    assert_same_result(o, g, "16x400 NS global")
+
+
+def test_global_schedule_edge_cases():
+    for (F, B, V, M, it) in ((10, 2, 3, 0, 4), (10, 1, 1, 1, 4), (40, 1, 1, 65, 40), (30, 3, 5, 40, 80)):
+        inst = make_instance(21 + M, F, B, V, M)
+        _, o = oracle_solve(inst, tenure=5, iters=it)
+        g = at.solve(_dev(inst), tenure=5, iters=it, schedule=at.SCHED_GLOBAL, n_groups=3)
+        assert_same_result(o, g, f"global {V}x{M}")
+
+
+def test_stress_instance_prefix():
+    """The 256-vehicle x 10000-mission instance: greedy start and the first
+    iterations against the oracle (each oracle iteration scores 1.5e8 moves)."""
+    inst = stress_instance(0)
+    iters = 3
+    _, o = oracle_solve(inst, tenure=25, iters=iters)
+    g = at.solve(_dev(inst), tenure=25, iters=iters)
+    assert_same_result(o, g, "256x10000 prefix")
