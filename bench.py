@@ -53,6 +53,8 @@ def parse():
                     help="also run the serving stream at these arrival rates (req/s, comma separated)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--groups", type=int, default=0)
     return ap.parse_args()
@@ -96,6 +98,18 @@ def main():
     from gen.instances import m400_instance
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size, run before the benchmark in the same process:
+        # FETCH_SIZE / WRITE_SIZE of this kernel give the counter-to-bytes factor
+        # used to scale the search kernel's counters
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     inst = m400_instance(0)
     M, V, ITERS, TEN = inst.n_missions, inst.n_vehicles, 5000, 15
     lat = torch.tensor(inst.lat, dtype=torch.float64, device="cuda")

@@ -168,8 +168,9 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params,
  * on the GPU: the device advances every resident solve `chunk_iters`
  * iterations per launch, so requests that arrive while others run start
  * within one chunk.  Each request's result is the same as at_solve's.
- * at_server_submit copies what it needs from the instance (device arrays are
- * read on the server's stream before it returns) and returns a ticket;
+ * at_server_submit returns a ticket; the instance's device arrays are read
+ * when the request is admitted, so the caller keeps them valid until
+ * at_server_poll has returned the result;
  * at_server_poll returns AT_OK with the result when done (out's arrays are
  * device memory of the caller, filled then), AT_EAGAIN while pending;
  * at_server_progress drives the device (call it from one thread, in a loop);

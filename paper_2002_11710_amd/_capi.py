@@ -296,7 +296,8 @@ class Server:
         _check(lib().at_server_submit(self._h, C.byref(ci), C.byref(pr), C.byref(ticket)))
         bufs = _alloc_result(inst.n_missions, inst.n_vehicles, pr.max_iters, bool(pr.trace),
                              inst.travel.device)
-        self._pending[ticket.value] = (bufs, inst.n_missions)
+        # the instance's device arrays are read at admission: keep them alive until polled
+        self._pending[ticket.value] = (bufs, inst.n_missions, inst)
         return ticket.value
 
     def progress(self) -> int:
@@ -305,7 +306,7 @@ class Server:
         return n.value
 
     def poll(self, ticket: int):
-        bufs, M = self._pending[ticket]
+        bufs, M, _inst = self._pending[ticket]
         res = _c_result(bufs)
         rc = lib().at_server_poll(self._h, C.c_uint64(ticket), C.byref(res))
         if rc == AT_EAGAIN:

@@ -237,7 +237,7 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
         const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
         int g = h.pr.n_groups ? h.pr.n_groups
                               : (int)std::max<int64_t>(1, std::min<int64_t>(32, h.slots / 8192));
-        g = std::min(g, std::min(cap, num_cus()));
+        g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
         if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
         h.kind = AT_SCHED_MULTI;
         h.groups = g;
@@ -323,6 +323,9 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         }
         if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
         if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
+        if (hf.kind == AT_SCHED_MULTI &&
+            (e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups, s)) != hipSuccess)
+            return hip_fail(e, "reset exchange");
         if (hf.kind == AT_SCHED_MULTI)
             e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
         else

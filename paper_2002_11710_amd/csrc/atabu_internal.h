@@ -50,6 +50,7 @@ constexpr int32_t kMaxTravel = 1 << 23;       // travel times must be below this
 constexpr int kMaxLocs = 65535;
 constexpr int kMaxMissions = 65535;
 constexpr int kMaxVehicles = 65535;
+constexpr int kMaxGroups = 256;               // workgroups of one cooperative solve
 
 struct InstDev {
     // filled by the host
@@ -119,6 +120,9 @@ struct Xchg {
     uint32_t queue;                   // next job of the one-workgroup-per-job schedule
     uint32_t pad[3];
     int64_t init_obj;                 // greedy objective, published by workgroup 0
+    // per-workgroup argmin slots of the multi-workgroup schedule, double-buffered by
+    // iteration parity; bit 63 carries the iteration's tag (bit 1 of the iteration)
+    uint64_t slots[2][kMaxGroups];
 };
 
 struct Lay {

@@ -67,6 +67,25 @@ __device__ __forceinline__ uint64_t pack_key(bool blocked, int delta, uint32_t i
     return ((uint64_t)blocked << 63) | ((uint64_t)(uint32_t)(delta + kDeltaBias) << 32) | idx;
 }
 
+// 64-bit key <-> exchange slot: the slot keeps the key's order in its low 63
+// bits (blocked, delta + 2^29, index; |delta| < 2^29) and the tag in bit 63.
+__device__ __forceinline__ uint64_t encode_slot(uint64_t key, uint64_t tag)
+{
+    if (key == kKeyNone) return (tag << 63) | 0x7FFFFFFFFFFFFFFFull;
+    const uint64_t bl = key >> 63;
+    const uint64_t f = ((key >> 32) & 0x7FFFFFFFull) - (1ull << 29);
+    return (tag << 63) | (bl << 62) | (f << 32) | (key & 0xFFFFFFFFull);
+}
+
+__device__ __forceinline__ uint64_t decode_slot(uint64_t v)
+{
+    const uint64_t low = v & 0x7FFFFFFFFFFFFFFFull;
+    if (low == 0x7FFFFFFFFFFFFFFFull) return kKeyNone;
+    const uint64_t bl = (low >> 62) & 1;
+    const uint64_t f = ((low >> 32) & 0x3FFFFFFFull) + (1ull << 29);
+    return (bl << 63) | (f << 32) | (low & 0xFFFFFFFFull);
+}
+
 __device__ __forceinline__ uint32_t swap_index(uint32_t R, uint32_t M, uint32_t a, uint32_t b)
 {
     // a < b
@@ -145,21 +164,39 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
         const int Gend = min(G1, c.off[r + 1] + r + 1);
         const bool tb = use_tabu && (int)tabu[r * c.M + m] > t;
         uint32_t pm = 0xFFFFFFFFu;
+        // four columns per step: all their LDS reads are in flight together
+#define AT_RELOC(gv, Gv) \
+    min(pm, ((uint32_t)(remb + (int)tc[(gv).x + mc] + (int)tc[mr + (gv).y] - (gv).z) << 6) | (uint32_t)((Gv) - G0))
         if (r < rlo || r > rhi) {
             // no lane of this tile flies vehicle r: no gap is a lane's own
+            for (; G + 4 <= Gend; G += 4) {
+                const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+                pm = AT_RELOC(g0, G);
+                pm = AT_RELOC(g1, G + 1);
+                pm = AT_RELOC(g2, G + 2);
+                pm = AT_RELOC(g3, G + 3);
+            }
             for (; G < Gend; ++G) {
-                const int4 g = c.gap[G];
-                const int d = remb + (int)tc[g.x + mc] + (int)tc[mr + g.y] - g.z;
-                pm = min(pm, ((uint32_t)d << 6) | (uint32_t)(G - G0));
+                const int4 g0 = c.gap[G];
+                pm = AT_RELOC(g0, G);
             }
         } else {
+            for (; G + 4 <= Gend; G += 4) {
+                const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+                const uint32_t p0 = AT_RELOC(g0, G), p1 = AT_RELOC(g1, G + 1);
+                const uint32_t p2 = AT_RELOC(g2, G + 2), p3 = AT_RELOC(g3, G + 3);
+                pm = ((unsigned)(G - Gi) >= 2u) ? p0 : pm;
+                pm = ((unsigned)(G + 1 - Gi) >= 2u) ? min(pm, p1) : pm;
+                pm = ((unsigned)(G + 2 - Gi) >= 2u) ? min(pm, p2) : pm;
+                pm = ((unsigned)(G + 3 - Gi) >= 2u) ? min(pm, p3) : pm;
+            }
             for (; G < Gend; ++G) {
-                const int4 g = c.gap[G];
-                const int d = remb + (int)tc[g.x + mc] + (int)tc[mr + g.y] - g.z;
-                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)(G - G0);
-                pm = ((unsigned)(G - Gi) >= 2u) ? min(pm, p) : pm;
+                const int4 g0 = c.gap[G];
+                const uint32_t p0 = AT_RELOC(g0, G);
+                pm = ((unsigned)(G - Gi) >= 2u) ? p0 : pm;
             }
         }
+#undef AT_RELOC
         if (act && pm != 0xFFFFFFFFu) {
             const int d = (int)(pm >> 6) - kPackBias;
             const int Gw = G0 + (int)(pm & 63u);
@@ -189,23 +226,34 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     // partners at or before the lane, or directly after it, need the masked path
     const bool diag = j0 <= tl * kWave + kWave;
     const TB *tabu_ri = tabu + ri * c.M;
+    const int th = use_tabu ? t : INT32_MAX;     // no entry exceeds INT32_MAX: nothing is tabu
     uint64_t best = kKeyNone;
     int j = j0;
     while (j < j1) {
         const int r = c.posB[j].z >> 16;
         const int jend = min(j1, c.off[r + 1]);
-        const bool t1 = use_tabu && (int)tabu[r * c.M + mi] > t;
+        const bool t1 = (int)tabu[r * c.M + mi] > th;
         uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
         if (!diag) {
-            for (; j < jend; ++j) {
-                const int4 a = c.posA[j], b = c.posB[j];
-                const int d = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
-                            + (int)tc[a.z + mci] + (int)tc[mri + a.w];
-                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)b.w;
-                const bool tb = t1 || (use_tabu && (int)tabu_ri[b.z & 0xFFFF] > t);
-                mT = tb ? min(mT, p) : mT;
-                mF = tb ? mF : min(mF, p);
+#define AT_SWAP(a, b)                                                                          \
+    do {                                                                                       \
+        const int d_ = outb - (b).x + (int)tc[xri + (a).y] + (int)tc[(a).x + yci]              \
+                     + (int)tc[(a).z + mci] + (int)tc[mri + (a).w];                            \
+        const uint32_t p_ = ((uint32_t)d_ << 6) | (uint32_t)(b).w;                             \
+        const bool tb_ = t1 | ((int)tabu_ri[(b).z & 0xFFFF] > th);                             \
+        mT = tb_ ? min(mT, p_) : mT;                                                           \
+        mF = tb_ ? mF : min(mF, p_);                                                           \
+    } while (0)
+            for (; j + 2 <= jend; j += 2) {
+                const int4 a0 = c.posA[j], b0 = c.posB[j], a1 = c.posA[j + 1], b1 = c.posB[j + 1];
+                AT_SWAP(a0, b0);
+                AT_SWAP(a1, b1);
             }
+            for (; j < jend; ++j) {
+                const int4 a0 = c.posA[j], b0 = c.posB[j];
+                AT_SWAP(a0, b0);
+            }
+#undef AT_SWAP
         } else {
             for (; j < jend; ++j) {
                 const int4 a = c.posA[j], b = c.posB[j];
@@ -219,7 +267,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
                       + (int)tc[a.z + mci] + (int)tc[mri + a.w];
                 }
                 const uint32_t p = ((uint32_t)d << 6) | (uint32_t)b.w;
-                const bool tb = t1 || (use_tabu && (int)tabu_ri[b.z & 0xFFFF] > t);
+                const bool tb = t1 | ((int)tabu_ri[b.z & 0xFFFF] > th);
                 const bool ok = j > i;
                 mT = (ok && tb) ? min(mT, p) : mT;
                 mF = (ok && !tb) ? min(mF, p) : mF;
@@ -501,29 +549,38 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
             w = wave_min(w);
-            if (MULTI && lane == 0) {
-                uint64_t *slot = &xs->key[t % 3];
-                __hip_atomic_fetch_min(slot, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&xs->cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t target = (uint32_t)nwg * (uint32_t)(t - J.t_begin + 1);
-                uint32_t spins = 0;
-                uint32_t ab = 0;
-                while (__hip_atomic_load(&xs->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                    ab = __hip_atomic_load(&xs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (ab) break;
-                    if (++spins > kSpinLimit) {
-                        __hip_atomic_store(&xs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ab = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                w = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (wg == 0)
-                    __hip_atomic_store(&xs->key[(t + 2) % 3], kKeyNone, __ATOMIC_RELAXED,
+            if (MULTI) {
+                // Each workgroup publishes its minimum in its own slot, tagged with
+                // bit 1 of the iteration; wave 0 of every workgroup polls all slots
+                // (one lane per slot) until every tag matches.  A workgroup can be at
+                // most one iteration ahead of another, so parity buffers plus the tag
+                // never confuse iterations t and t+2.
+                const int rel = t - J.t_begin;
+                const uint64_t tag = (uint64_t)((rel >> 1) & 1);
+                uint64_t *slots = xs->slots[rel & 1];
+                if (lane == 0)
+                    __hip_atomic_store(&slots[wg], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                c.red[65] = ab;
+                uint64_t bestk = kKeyNone;
+                uint32_t ab = 0;
+                for (int base = 0; base < nwg && !ab; base += kWave) {
+                    const int w2 = base + lane;
+                    bool ready = w2 >= nwg;
+                    uint64_t v = 0;
+                    uint32_t spins = 0;
+                    for (;;) {
+                        if (!ready) {
+                            v = __hip_atomic_load(&slots[w2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ready = (v >> 63) == tag;
+                        }
+                        if (__all(ready)) break;
+                        if (++spins > kSpinLimit) { ab = 1; break; }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (w2 < nwg && ready) bestk = umin64(bestk, decode_slot(v));
+                }
+                w = wave_min(bestk);
+                if (lane == 0) c.red[65] = ab;
             }
             if (lane == 0) c.red[64] = w;
         }

@@ -99,7 +99,7 @@ def test_budget_admission_and_late_arrivals():
 
 
 def test_oversized_request_rejected():
-    inst = make_instance(9, 300, 10, 20, 250)
+    inst = make_instance(9, 1500, 25, 50, 1000)      # its compact travel block alone exceeds 4 MB
     srv = at.Server(2 << 20, max_slots=4, chunk_iters=10)
     with pytest.raises(at.AtError) as e:
         srv.submit(_dev(inst), iters=100, tenure=5)
