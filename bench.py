@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serve", type=str, default="",
                     help="also run the serving stream at these arrival rates (req/s, comma separated)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--stress", type=int, default=0,
+                    help="also run the 256 x 10000 stress instance for this many iterations (Tabu and NS)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
@@ -196,6 +198,8 @@ def main():
     }
     if args.batch:
         line["batch"] = bench_batch(args.batch)
+    if args.stress:
+        line["stress"] = bench_stress(args.stress)
     if args.serve:
         line["serving"] = [bench_serve(float(x), args.serve_requests) for x in args.serve.split(",")]
     if not args.no_cpu:
@@ -235,10 +239,58 @@ def bench_batch(n_inst: int, restarts: int = 8):
         ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
     kms = float(res[0]["search_ms"])
     assert all(r["status"] == 0 for r in res)
+    # the plain per-instance form: one at_solve launch per (instance, restart), in
+    # sequence on one stream, on a sample of the same solves (identical results)
+    from gen.instances import restart_seed
+    n_plain = min(len(res), 64)
+    pairs = [(k // restarts, k % restarts) for k in range(n_plain)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [at.solve(devs[i], variant=at.AT_TABU, tenure=specs[i]["tenure"], iters=specs[i]["iters"],
+                      restart_seed=restart_seed(specs[i]["seed"], r), trace=False) for i, r in pairs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for (i, r), p in zip(pairs, plain):
+        b = res[i * restarts + r]
+        assert p["best_obj"] == b["best_obj"] and torch.equal(p["route_seq"], b["route_seq"])
+    plain_work = sum(move_counts(specs[i]["n_missions"], specs[i]["n_vehicles"])[0]
+                     + move_counts(specs[i]["n_missions"], specs[i]["n_vehicles"])[1] for i, _ in pairs)
+    all_work = sum(restarts * sum(move_counts(s["n_missions"], s["n_vehicles"])) for s in specs)
+    # plain solves/s for this batch's mix: the sample's move-eval rate applied to all solves
+    plain_evals_per_s = plain_work * 2000 / t_plain
+    plain_sps = plain_evals_per_s / (all_work * 2000 / len(res))
     return {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
             "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
             "move_evals_per_s": evals / wall, "search_ms": kms,
-            "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS}
+            "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS,
+            "plain_sample_solves": n_plain, "plain_sample_s": t_plain,
+            "plain_solves_per_s": plain_sps,
+            "speedup_vs_plain": (n_inst * restarts / wall) / plain_sps}
+
+
+def bench_stress(iters: int):
+    """256 vehicles x 10000 missions (2000 facilities, 200 bases), tenure 25:
+    Tabu search and neighbourhood search on the HBM-resident schedule."""
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import stress_instance
+
+    inst = stress_instance(0)
+    dev = at.DeviceInstance.from_instance(inst)
+    rel, swp = move_counts(inst.n_missions, inst.n_vehicles)
+    out = {"iters": iters, "moves_per_iter": rel + swp}
+    for name, variant in (("tabu", at.AT_TABU), ("ns", at.AT_NS)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = at.solve(dev, variant=variant, tenure=25, iters=iters, trace=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert g["status"] == 0
+        out[name] = {"best_obj": int(g["best_obj"]), "iters_done": int(g["iters_done"]),
+                     "search_ms": float(g["search_ms"]), "wall_s": wall,
+                     "move_evals_per_s": (rel + swp) * g["iters_done"] / (g["search_ms"] / 1000.0)}
+    return out
 
 
 def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,

@@ -1,0 +1,86 @@
+"""Autotuner for the one-workgroup-per-solve schedule.
+
+For size buckets of move slots per iteration it times uneven batches (drawn
+from the batch size law of gen.instances) under every launch shape
+(threads per workgroup x columns per work unit), keeps the fastest shape per
+bucket, and writes csrc/tuned_table.h; rebuild the library afterwards
+(paper_2002_11710_amd/build.py).  Every shape gives identical results, so the
+table only changes speed.  Needs the GPU.
+
+Usage: python -m paper_2002_11710_amd.autotune [--iters 200] [--per-bucket 96]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+BUCKETS = [(0, 4000), (4000, 12000), (12000, 30000), (30000, 60000), (60000, 100000),
+           (100000, 1 << 62)]
+SHAPES = [(b, c) for b in (256, 512, 1024) for c in (8, 16, 32)]
+
+
+def slots(m, v):
+    return m * (m + v) + m * (m - 1) // 2
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--per-bucket", type=int, default=512)
+    ap.add_argument("--restarts", type=int, default=4)
+    ap.add_argument("--out", default=os.path.join(HERE, "csrc", "tuned_table.h"))
+    args = ap.parse_args()
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import batch_instance, batch_specs
+
+    # enough solves per bucket (per-bucket x restarts, default 2048) to fill every CU
+    # several times over, so the shape that maximises throughput wins
+    specs = batch_specs(60000)
+    rows = []
+    for lo, hi in BUCKETS:
+        pick = [s for s in specs if lo <= slots(s["n_missions"], s["n_vehicles"]) < hi]
+        pick = pick[: args.per_bucket]
+        if not pick:
+            continue
+        devs = [at.DeviceInstance.from_instance(batch_instance(s)) for s in pick]
+        best = None
+        for block, chunk in SHAPES:
+            params = [at._capi.make_params(at.AT_TABU, s["tenure"], args.iters, True, s["seed"],
+                                           False, at.SCHED_WG, 0, block, chunk) for s in pick]
+            at.solve_batch(devs, params, args.restarts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            at.solve_batch(devs, params, args.restarts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            print(json.dumps(dict(bucket=[lo, hi], block=block, chunk=chunk, s=round(dt, 4))),
+                  flush=True)
+            if best is None or dt < best[0]:
+                best = (dt, block, chunk)
+        rows.append((hi, best[1], best[2]))
+    lines = ["// tuned_table.h -- default launch shape of the one-workgroup-per-solve schedule",
+             "// by move slots per iteration (M*(M+V) + M*(M-1)/2).  Rows are tried in order;",
+             "// the first row whose max_slots exceeds the solve's slots applies.",
+             "// Written by paper_2002_11710_amd/autotune.py from timings on gfx950.",
+             "#pragma once", "#include <cstdint>", "", "namespace at {",
+             "struct TunedRow { int64_t max_slots; int block; int chunk; };",
+             "static const TunedRow kTuned[] = {"]
+    for hi, b, c in rows:
+        lim = "INT64_MAX" if hi >= (1 << 62) else str(hi)
+        lines.append(f"    {{{lim}, {b}, {c}}},")
+    lines += ["};", "}  // namespace at", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -17,6 +17,7 @@
 #include "atabu.h"
 #include "atabu_internal.h"
 #include "engine.h"
+#include "tuned_table.h"
 
 namespace at {
 
@@ -198,18 +199,22 @@ int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, 
 // ---------------------------------------------------------------------------
 // schedule
 // ---------------------------------------------------------------------------
-static int pick_chunk(const at_params &pr, int64_t M)
-{
-    if (pr.chunk) return pr.chunk;
-    return M >= 256 ? 32 : 16;
-}
-
+// Default block size and column chunk by move slots per iteration, from the
+// table the autotuner writes (paper_2002_11710_amd/autotune.py).
 static int pick_block(const at_params &pr, int64_t slots)
 {
     if (pr.block) return pr.block;
-    if (slots >= 60000) return 1024;
-    if (slots >= 8000) return 512;
-    return 256;
+    for (const TunedRow &r : kTuned)
+        if (slots < r.max_slots) return r.block;
+    return 1024;
+}
+
+static int pick_chunk(const at_params &pr, int64_t slots)
+{
+    if (pr.chunk) return pr.chunk;
+    for (const TunedRow &r : kTuned)
+        if (slots < r.max_slots) return r.chunk;
+    return 32;
 }
 
 int plan_job(JobHost &h, const InstDev &d, bool alone)
@@ -219,7 +224,7 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     h.esz16 = d.esz == 2 ? 1 : 0;
     h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
     h.block = pick_block(h.pr, h.slots);
-    h.chunk = pick_chunk(h.pr, d.M);
+    h.chunk = pick_chunk(h.pr, h.slots);
     h.groups = 1;
     if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit) {
         if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
@@ -234,9 +239,13 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     }
     h.kind = AT_SCHED_WG;
     if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
+        // measured on gfx950 (16 x 400 missions): 512 threads, 16-column units and
+        // about one workgroup per 3840 move slots, up to 64 workgroups
+        if (!h.pr.block) h.block = 512;
+        if (!h.pr.chunk) h.chunk = 16;
         const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
         int g = h.pr.n_groups ? h.pr.n_groups
-                              : (int)std::max<int64_t>(1, std::min<int64_t>(32, h.slots / 8192));
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(64, h.slots / 3840));
         g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
         if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
         h.kind = AT_SCHED_MULTI;
@@ -291,36 +300,89 @@ int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> 
     return AT_OK;
 }
 
+// Internal streams on which the one-workgroup-per-job launches of different
+// size classes run concurrently (forked from and joined back to the caller's
+// stream with events).  Default priority, created once.
+static hipStream_t class_stream(int k)
+{
+    static hipStream_t pool[kMaxClasses] = {};
+    static bool made[kMaxClasses] = {};
+    if (!made[k]) {
+        if (hipStreamCreateWithFlags(&pool[k], hipStreamNonBlocking) != hipSuccess) return nullptr;
+        made[k] = true;
+    }
+    return pool[k];
+}
+
 // Launch every job of `dj` (device table in the order of `order`).  Jobs of
-// the one-workgroup schedule share one persistent launch per kernel class;
-// multi-workgroup and HBM-resident jobs get a cooperative launch each.
+// the one-workgroup schedule share one persistent launch per class (entry
+// width, tabu width, block size); the classes run concurrently on internal
+// streams.  Multi-workgroup and HBM-resident jobs get a cooperative launch
+// each, in order, on the caller's stream.
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
                 Xchg *xs, hipStream_t s)
 {
     hipError_t e;
     const int n = (int)order.size();
+    struct Cls { int k0, k1, block, tb16, esz16; uint32_t lds; };
+    std::vector<Cls> cls;
     int k = 0;
-    while (k < n) {
+    while (k < n && jobs[(size_t)order[(size_t)k]].kind == AT_SCHED_WG) {
         const JobHost &hf = jobs[(size_t)order[(size_t)k]];
-        if (hf.kind == AT_SCHED_WG) {
-            int k1 = k, block = 256;
-            uint32_t lds = 0;
-            while (k1 < n) {
-                const JobHost &h = jobs[(size_t)order[(size_t)k1]];
-                if (h.kind != AT_SCHED_WG || h.esz16 != hf.esz16 || h.tb16 != hf.tb16) break;
-                lds = std::max(lds, h.lds);
-                block = std::max(block, h.block);
-                ++k1;
-            }
-            const int count = k1 - k;
-            if ((e = fill_u32(&xs->queue, 0u, 1, s)) != hipSuccess) return hip_fail(e, "reset queue");
-            const int per_cu = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(lds, 1)));
-            const int grid = std::max(1, std::min(count, num_cus() * std::min(per_cu, 8)));
-            if ((e = launch_search_wg(dj + k, count, xs, grid, block, lds, hf.tb16, hf.esz16, s)) != hipSuccess)
-                return hip_fail(e, "search launch");
-            k = k1;
-            continue;
+        Cls c{k, k, hf.block, hf.tb16, hf.esz16, 0};
+        while (c.k1 < n) {
+            const JobHost &h = jobs[(size_t)order[(size_t)c.k1]];
+            if (h.kind != AT_SCHED_WG || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block) break;
+            c.lds = std::max(c.lds, h.lds);
+            ++c.k1;
         }
+        cls.push_back(c);
+        k = c.k1;
+    }
+    if ((int)cls.size() > kMaxClasses) return fail(AT_EINVAL, "too many launch classes");
+    if (!cls.empty()) {
+        if ((e = fill_u32(xs->queues, 0u, kMaxClasses, s)) != hipSuccess) return hip_fail(e, "reset queues");
+        hipEvent_t fork = nullptr;
+        std::vector<hipEvent_t> joins(cls.size(), nullptr);
+        const bool split = cls.size() > 1;
+        if (split) {
+            if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventRecord(fork, s)) != hipSuccess) return hip_fail(e, "event");
+        }
+        int rc = AT_OK;
+        for (size_t c = 0; c < cls.size() && rc == AT_OK; ++c) {
+            const Cls &q = cls[c];
+            hipStream_t st = s;
+            if (split) {
+                st = class_stream((int)c);
+                if (!st) { rc = fail(AT_EDEVICE, "cannot create a class stream"); break; }
+            }
+            if (split && (e = hipStreamWaitEvent(st, fork, 0)) != hipSuccess) { rc = hip_fail(e, "fork"); break; }
+            const int count = q.k1 - q.k0;
+            const int by_lds = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(q.lds, 1)));
+            const int by_waves = std::max(1, 16 * kWave / q.block);
+            const int per_cu = std::min(by_lds, by_waves);
+            const int grid = std::max(1, std::min(count, num_cus() * per_cu));
+            if ((e = launch_search_wg(dj + q.k0, count, &xs->queues[c], grid, q.block, q.lds, q.tb16,
+                                      q.esz16, st)) != hipSuccess) {
+                rc = hip_fail(e, "search launch");
+                break;
+            }
+            if (split) {
+                if ((e = hipEventCreateWithFlags(&joins[c], hipEventDisableTiming)) != hipSuccess ||
+                    (e = hipEventRecord(joins[c], st)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(s, joins[c], 0)) != hipSuccess) {
+                    rc = hip_fail(e, "join");
+                    break;
+                }
+            }
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipEvent_t ev : joins) if (ev) (void)hipEventDestroy(ev);
+        if (rc) return rc;
+    }
+    for (; k < n; ++k) {
+        const JobHost &hf = jobs[(size_t)order[(size_t)k]];
         if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
         if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
         if (hf.kind == AT_SCHED_MULTI &&
@@ -331,13 +393,13 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         else
             e = launch_search_global(dj + k, xs, hf.groups, hf.block, hf.tb16, hf.esz16, s);
         if (e != hipSuccess) return hip_fail(e, "cooperative search launch");
-        ++k;
     }
     return AT_OK;
 }
 
-// Order jobs: one-workgroup jobs grouped by kernel class, largest first (the
-// queue of each class hands its jobs out in this order), then the rest.
+// Order jobs: one-workgroup jobs grouped by launch class (entry width, tabu
+// width, block), largest first inside a class (its queue hands jobs out in
+// this order), then the cooperative ones.
 std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
 {
     const int n = (int)jobs.size();
@@ -345,9 +407,12 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
     for (int k = 0; k < n; ++k) order[(size_t)k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const JobHost &x = jobs[(size_t)a], &y = jobs[(size_t)b];
-        const int cx = x.kind == AT_SCHED_WG ? x.esz16 * 2 + x.tb16 : 4 + x.kind;
-        const int cy = y.kind == AT_SCHED_WG ? y.esz16 * 2 + y.tb16 : 4 + y.kind;
+        const int cx = x.kind == AT_SCHED_WG ? 0 : x.kind, cy = y.kind == AT_SCHED_WG ? 0 : y.kind;
         if (cx != cy) return cx < cy;
+        if (x.kind == AT_SCHED_WG) {
+            const int kx = (x.esz16 * 2 + x.tb16) * 4096 + x.block, ky = (y.esz16 * 2 + y.tb16) * 4096 + y.block;
+            if (kx != ky) return kx > ky;
+        }
         return x.slots > y.slots;
     });
     return order;
@@ -529,7 +594,7 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     h.out.route_off = (int32_t *)route_off;
     h.out.route_seq = (int32_t *)route_seq;
     h.slots = n_slots(d.M, d.V);
-    h.chunk = pick_chunk(*params, d.M);
+    h.chunk = pick_chunk(*params, h.slots);
     h.tb16 = 0;
     h.gstate = nullptr;
     JobDev j;

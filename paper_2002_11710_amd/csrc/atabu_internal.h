@@ -51,6 +51,7 @@ constexpr int kMaxLocs = 65535;
 constexpr int kMaxMissions = 65535;
 constexpr int kMaxVehicles = 65535;
 constexpr int kMaxGroups = 256;               // workgroups of one cooperative solve
+constexpr int kMaxClasses = 16;               // concurrent one-workgroup-per-job launches
 
 struct InstDev {
     // filled by the host
@@ -117,12 +118,13 @@ struct Xchg {
     uint64_t key[3];
     uint32_t cnt;                     // grid-barrier arrivals (monotone within a launch)
     uint32_t abort;                   // set by a workgroup whose wait ran out
-    uint32_t queue;                   // next job of the one-workgroup-per-job schedule
+    uint32_t queue;                   // (unused slot kept for layout)
     uint32_t pad[3];
     int64_t init_obj;                 // greedy objective, published by workgroup 0
     // per-workgroup argmin slots of the multi-workgroup schedule, double-buffered by
     // iteration parity; bit 63 carries the iteration's tag (bit 1 of the iteration)
     uint64_t slots[2][kMaxGroups];
+    uint32_t queues[kMaxClasses];     // next job of each one-workgroup-per-job launch
 };
 
 struct Lay {
@@ -193,7 +195,7 @@ __host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M
 hipError_t launch_travel(int32_t n, const double *lat, const double *lon, double speed,
                          int32_t *out, hipStream_t s);
 hipError_t launch_prepare(InstDev *insts, int32_t n, hipStream_t s);
-hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, Xchg *xs, int grid, int block,
+hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid, int block,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);

@@ -949,18 +949,18 @@ __global__ void __launch_bounds__(1024) k_search_global(const JobDev *job, Xchg 
 
 // One workgroup per job; jobs are taken from an atomic queue until exhausted.
 template <typename TE, typename TB>
-__global__ void __launch_bounds__(1024) k_search_wg(const JobDev *jobs, int n_jobs, Xchg *xs)
+__global__ void __launch_bounds__(1024) k_search_wg(const JobDev *jobs, int n_jobs, uint32_t *queue)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ int s_job;
     for (;;) {
         if (threadIdx.x == 0)
-            s_job = (int)__hip_atomic_fetch_add(&xs->queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_job = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int j = s_job;
         __syncthreads();
         if (j >= n_jobs) return;
-        run_job<TE, TB, false>(jobs[j], smem, 0, 1, xs);
+        run_job<TE, TB, false>(jobs[j], smem, 0, 1, nullptr);
         __syncthreads();
     }
 }
@@ -1031,7 +1031,7 @@ static hipError_t set_lds(F *f, uint32_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, Xchg *xs, int grid, int block,
+hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid, int block,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s)
 {
     hipError_t e;
@@ -1039,7 +1039,7 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, Xchg *xs, int gr
     do {                                                                                   \
         if ((e = set_lds(k_search_wg<TE, TB>, lds_bytes)) != hipSuccess) return e;         \
         hipLaunchKernelGGL((k_search_wg<TE, TB>), dim3(grid), dim3(block), lds_bytes, s,   \
-                           jobs, n_jobs, xs);                                              \
+                           jobs, n_jobs, queue);                                           \
     } while (0)
     if (esz16 && tb16) AT_WG(uint16_t, uint16_t);
     else if (esz16) AT_WG(uint16_t, int32_t);
