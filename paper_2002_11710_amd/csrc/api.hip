@@ -88,13 +88,13 @@ bool may_need_global(const at_instance &in, const at_params &pr)
     return worst > kLdsLimit;
 }
 
-size_t inst_bytes(const at_instance &in)
+size_t inst_bytes(const at_instance &in, bool with_t)
 {
     size_t o = 0;
     o += al256(4 * (size_t)in.n_locs) * 2;
     o += al256(4 * (size_t)in.n_missions) * 2;
     o += al256(4 * (size_t)in.n_vehicles) * 2;
-    o += al256((size_t)tc_capacity(in.n_locs, in.n_missions, in.n_vehicles));
+    o += al256((size_t)tc_capacity(in.n_locs, in.n_missions, in.n_vehicles)) * (with_t ? 2 : 1);
     return o;
 }
 
@@ -103,7 +103,7 @@ size_t gstate_bytes(const at_instance &in, const at_params &pr)
     return al256(sizeof(GlobalBufs)) + al256(global_state_bytes(in.n_missions, in.n_vehicles, tabu_bytes(pr)));
 }
 
-void carve_inst(InstDev &d, const at_instance &in, char *base)
+void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
 {
     size_t o = 0;
     d.L = in.n_locs; d.M = in.n_missions; d.V = in.n_vehicles;
@@ -116,6 +116,8 @@ void carve_inst(InstDev &d, const at_instance &in, char *base)
     d.vcol = (int32_t *)(base + o); o += al256(4 * (size_t)in.n_vehicles);
     d.tc = (void *)(base + o);
     d.tc_cap = tc_capacity(in.n_locs, in.n_missions, in.n_vehicles);
+    o += al256((size_t)d.tc_cap);
+    d.tct = with_t ? (void *)(base + o) : nullptr;
     d.status = AT_EDEVICE;
 }
 
@@ -135,6 +137,7 @@ void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
     g.posA = (int4 *)(base + o); o += a(16 * uM);
     g.posB = (int4 *)(base + o); o += a(16 * uM);
     g.gap = (int4 *)(base + o); o += a(16 * (uM + uV));
+    g.posC = (int2 *)(base + o); o += a(8 * uM);
     g.prank = (uint8_t *)(base + o); o += a(uM);
     g.tabu = (void *)(base + o);
     g.cur = 0;
@@ -156,7 +159,10 @@ static WsPlan plan_ws(int32_t n_inst, const at_instance *insts, const at_params 
     p.xchg = o; o = al256(o + sizeof(Xchg));
     p.insts = o; o = al256(o + sizeof(InstDev) * (size_t)n_inst);
     p.inst_off.resize((size_t)n_inst);
-    for (int32_t i = 0; i < n_inst; ++i) { p.inst_off[(size_t)i] = o; o += inst_bytes(insts[i]); }
+    for (int32_t i = 0; i < n_inst; ++i) {
+        p.inst_off[(size_t)i] = o;
+        o += inst_bytes(insts[i], may_need_global(insts[i], params[i]));
+    }
     p.jobs = o; o = al256(o + sizeof(JobDev) * (size_t)n_jobs);
     p.scal = o; o = al256(o + sizeof(JobScal) * (size_t)n_jobs);
     p.states = o; o = al256(o + sizeof(SolveState) * (size_t)n_jobs);
@@ -230,7 +236,18 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
         if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
         h.kind = AT_SCHED_GLOBAL;
         h.block = h.pr.block ? h.pr.block : 256;
-        const int cap = max_groups_global(h.block, h.tb16, h.esz16);
+        if (!d.tct) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but its transposed block was not reserved");
+        // as many missions per block and staged vehicle rows as LDS holds
+        h.gk = 0;
+        for (int K : {4, 2, 1}) {
+            for (int nrr : {2, 1, 0}) {
+                const uint32_t b = global_lds_bytes(K, nrr, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4);
+                if (b <= kLdsLimit) { h.gk = K; h.gnr = nrr; h.lds = b; break; }
+            }
+            if (h.gk) break;
+        }
+        if (!h.gk) return fail(AT_ENOMEM, "instance too large: %d exit and %d entry locations do not fit the staged search", d.R, d.C);
+        const int cap = max_groups_global(h.block, h.lds, h.tb16, h.esz16);
         if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
         const int g = h.pr.n_groups ? h.pr.n_groups
                                     : (int)std::max<int64_t>(1, std::min<int64_t>(num_cus(), h.slots / 16384));
@@ -282,6 +299,8 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.scal = scal;
     j.st = nullptr;
     j.gb = h.gstate;
+    j.gk = h.gk;
+    j.gnr = h.gnr;
     return AT_OK;
 }
 
@@ -391,7 +410,7 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         if (hf.kind == AT_SCHED_MULTI)
             e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
         else
-            e = launch_search_global(dj + k, xs, hf.groups, hf.block, hf.tb16, hf.esz16, s);
+            e = launch_search_global(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
         if (e != hipSuccess) return hip_fail(e, "cooperative search launch");
     }
     return AT_OK;
@@ -503,7 +522,8 @@ static int solve_common(int32_t n_inst, const at_instance *insts, const at_param
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
     std::vector<InstDev> ih((size_t)n_inst);
-    for (int32_t i = 0; i < n_inst; ++i) carve_inst(ih[(size_t)i], insts[i], base + p.inst_off[(size_t)i]);
+    for (int32_t i = 0; i < n_inst; ++i)
+        carve_inst(ih[(size_t)i], insts[i], base + p.inst_off[(size_t)i], may_need_global(insts[i], params[i]));
     int rc = prepare_instances(n_inst, (InstDev *)(base + p.insts), ih, s);
     if (rc) return rc;
     std::vector<JobHost> jobs((size_t)nj);
@@ -579,7 +599,7 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
     std::vector<InstDev> ih(1);
-    carve_inst(ih[0], *inst, base + p.inst_off[0]);
+    carve_inst(ih[0], *inst, base + p.inst_off[0], may_need_global(*inst, *params));
     rc = prepare_instances(1, (InstDev *)(base + p.insts), ih, s);
     if (rc) return rc;
     const InstDev &d = ih[0];

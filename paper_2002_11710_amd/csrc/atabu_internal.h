@@ -61,10 +61,12 @@ struct InstDev {
     int32_t *exit_loc, *enter_loc;    // workspace, L each
     int32_t *mrow, *mcol, *vrow, *vcol;
     void *tc;                         // workspace, capacity tc_cap bytes
+    void *tct;                        // transposed block (C rows, stride Rs) or null
     int64_t tc_cap;
     // filled by the prepare kernel
     int32_t status;
     int32_t R, C, Cs, esz;            // esz = 2 or 4 bytes per compact entry
+    int32_t Rs;                       // row stride of the transposed block
     int32_t maxT;
     int64_t svc_sum;
 };
@@ -88,6 +90,7 @@ struct GlobalBufs {
     uint16_t *seq[2], *rt[2], *pof[2], *rof[2];
     int32_t *off[2];
     int4 *posA, *posB, *gap;
+    int2 *posC;                       // per position: exit row of its delivery, of its predecessor
     uint8_t *prank;
     void *tabu;
     int32_t cur;                      // which buffer holds the current routes
@@ -101,7 +104,8 @@ struct JobDev {
     int32_t resume, save;             // load / store `st`
     int32_t tb16;                     // tabu entries stored as uint16 in LDS
     int32_t chunk;                    // columns per work unit
-    int32_t pad1;
+    int32_t gk;                       // global schedule: missions staged per block
+    int32_t gnr;                      // global schedule: vehicle tabu rows staged per block
     uint64_t seed;
     int32_t *out_off, *out_seq, *out_of;
     uint32_t *tr_move;
@@ -185,7 +189,7 @@ __host__ __device__ inline uint64_t global_state_bytes(int M, int V, int tbsz)
 {
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V, NG = uM + uV;
     auto a = [](uint64_t x) { return (x + 255u) & ~(uint64_t)255u; };
-    return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * a(16 * uM) + a(16 * NG) + a(uM)
+    return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * a(16 * uM) + a(16 * NG) + a(8 * uM) + a(uM)
          + a((uint64_t)tbsz * uM * uV);
 }
 
@@ -199,9 +203,21 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
-hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block, int tb16,
-                                int esz16, hipStream_t s);
-int max_groups_global(int block, int tb16, int esz16);
+hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
+int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
+// LDS bytes of the global schedule's mission-major eval: K missions' four
+// travel vectors, their tabu columns and nrr vehicle tabu rows.
+__host__ __device__ inline uint32_t global_lds_bytes(int K, int nrr, int R, int C, int M, int V,
+                                                     int esz, int tbsz)
+{
+    const uint64_t vec = (uint64_t)K * (2 * (uint64_t)R + 2 * (uint64_t)C) * (uint64_t)esz;
+    const uint64_t tk = (uint64_t)K * (uint64_t)V * (uint64_t)tbsz;
+    const uint64_t rr = (uint64_t)nrr * (uint64_t)M * (uint64_t)tbsz;
+    const uint64_t tot = al16((uint32_t)0) + ((vec + 15) & ~15ull) + ((tk + 15) & ~15ull)
+                       + ((rr + 15) & ~15ull) + 1024;
+    return tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
+}
 hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_t *seq,
                              const int32_t *tabu_until, int32_t t, int64_t cur, int64_t best,
                              uint64_t *keys, int block, uint32_t lds_bytes, int esz16,

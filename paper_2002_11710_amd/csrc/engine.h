@@ -27,6 +27,7 @@ struct JobHost {
     uint32_t lds = 0;
     int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
+    int gk = 0, gnr = 0;              // global schedule: staged missions / vehicle rows per block
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
 };
 
@@ -36,9 +37,9 @@ const char *last_error();
 int check_scalars(const at_instance *in, const at_params *pr);
 int tabu_bytes(const at_params &pr);
 bool may_need_global(const at_instance &in, const at_params &pr);
-size_t inst_bytes(const at_instance &in);
+size_t inst_bytes(const at_instance &in, bool with_t);
 size_t gstate_bytes(const at_instance &in, const at_params &pr);
-void carve_inst(InstDev &d, const at_instance &in, char *base);
+void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t);
 void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base);
 int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s);
 int plan_job(JobHost &h, const InstDev &d, bool alone);

@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     const int R = I.R, C = I.C;
     const int esz = s_max <= 65535 ? 2 : 4;
     const int Cs = compact_stride(C, esz);
-    if ((int64_t)R * Cs * esz > I.tc_cap) {
+    const int Rs = compact_stride(R, esz);
+    if ((int64_t)R * Cs * esz > I.tc_cap || (I.tct && (int64_t)C * Rs * esz > I.tc_cap)) {
         if (tid == 0) I.status = AT_ENOMEM;
         return;
     }
@@ -129,6 +130,23 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
             tc[k] = c < C ? T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : 0;
         }
     }
+    if (I.tct) {
+        // the same block transposed (entry-major), for the HBM-resident schedule
+        const int64_t tt = (int64_t)C * Rs;
+        if (esz == 2) {
+            uint16_t *tct = (uint16_t *)I.tct;
+            for (int64_t k = tid; k < tt; k += nthr) {
+                const int c = (int)(k / Rs), r = (int)(k - (int64_t)c * Rs);
+                tct[k] = r < R ? (uint16_t)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (uint16_t)0;
+            }
+        } else {
+            int32_t *tct = (int32_t *)I.tct;
+            for (int64_t k = tid; k < tt; k += nthr) {
+                const int c = (int)(k / Rs), r = (int)(k - (int64_t)c * Rs);
+                tct[k] = r < R ? T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : 0;
+            }
+        }
+    }
     for (int m = tid; m < M; m += nthr) {
         I.mrow[m] = rank_of(bmx, pfx, I.d[m]) * Cs;
         I.mcol[m] = rank_of(bme, pfe, I.p[m]);
@@ -140,6 +158,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     __syncthreads();
     if (tid == 0) {
         I.Cs = Cs;
+        I.Rs = Rs;
         I.esz = esz;
         I.maxT = s_max;
         I.svc_sum = (int64_t)s_svc;

@@ -42,9 +42,10 @@ struct Ctx {
     int32_t *mrow, *mcol, *vrow, *vcol, *off;
     uint16_t *seq, *rt, *rof, *pof;
     int4 *posA, *posB, *gap;
+    int2 *posC;     // global schedule only (row indices), else null
     uint8_t *prank;
     uint64_t *red;
-    int M, V, NG, chunk;
+    int M, V, NG, chunk, Cs;
     uint32_t R;   // relocate slots M*(M+V)
 };
 
@@ -118,25 +119,38 @@ template <typename TE>
 __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nthr)
 {
     const int CH = c.chunk;
+    const uint32_t Cs = (uint32_t)c.Cs;
     for (int i = tid; i < c.M; i += nthr) {
         const int m = c.seq[i], r = c.rt[i];
         const int x = (i == c.off[r]) ? c.vrow[r] : c.mrow[c.seq[i - 1]];
-        const int y = (i + 1 == c.off[r + 1]) ? c.vcol[r] : c.mcol[c.seq[i + 1]];
+        const bool last = i + 1 == c.off[r + 1];
+        const int y = last ? c.vcol[r] : c.mcol[c.seq[i + 1]];
         const int mc = c.mcol[m], mr = c.mrow[m];
         const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
         // rank of m among the missions of this position's chunk
         const int base = i - i % CH, end = min(c.M, base + CH);
         int rank = 0;
         for (int j = base; j < end; ++j) rank += c.seq[j] < m ? 1 : 0;
+        // swapping m with its successor in the same route: P m n N -> P n m N
+        int adj = 0;
+        if (!last) {
+            const int n = c.seq[i + 1];
+            const int y2 = (i + 2 == c.off[r + 1]) ? c.vcol[r] : c.mcol[c.seq[i + 2]];
+            const int mrn = c.mrow[n];
+            adj = l + (int)tc[mrn + mc] + (int)tc[mr + y2] - a - bb - (int)tc[mrn + y2];
+        }
         c.prank[base + rank] = (uint8_t)(i - base);
         c.posA[i] = make_int4(mr, mc, x, y);
-        c.posB[i] = make_int4(a + bb, l, m | (r << 16), rank);
-        c.gap[i + r] = make_int4(x, mc, a, r);
+        c.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
+                              (int)((uint32_t)rank | ((uint32_t)(adj + kPackBias) << 6)));
+        c.gap[i + r] = make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        if (c.posC) c.posC[i] = make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs));
     }
     for (int r = tid; r < c.V; r += nthr) {
         const int e = c.off[r + 1];
         const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
-        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]], r);
+        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]],
+                                 (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
     }
 }
 
@@ -152,7 +166,7 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
     const bool act = i < c.M;
     const int ii = act ? i : tl * kWave;
     const int4 pa = c.posA[ii], pb = c.posB[ii];
-    const int m = pb.z & 0xFFFF, ri = pb.z >> 16;
+    const int m = pb.z & 0xFFFF, ri = (int)((uint32_t)pb.z >> 16);
     const int mr = pa.x, mc = pa.y;
     const int remb = pb.y - pb.x + kPackBias;
     const int Gi = ii + ri;
@@ -160,7 +174,7 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
     uint64_t best = kKeyNone;
     int G = G0;
     while (G < G1) {
-        const int r = c.gap[G].w;
+        const int r = c.gap[G].w & 0xFFFF;
         const int Gend = min(G1, c.off[r + 1] + r + 1);
         const bool tb = use_tabu && (int)tabu[r * c.M + m] > t;
         uint32_t pm = 0xFFFFFFFFu;
@@ -219,9 +233,10 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     const bool act = i < c.M;
     const int ii = act ? i : tl * kWave;
     const int4 pa = c.posA[ii], pb = c.posB[ii];
-    const int mi = pb.z & 0xFFFF, ri = pb.z >> 16;
+    const int mi = pb.z & 0xFFFF, ri = (int)((uint32_t)pb.z >> 16);
     const int mri = pa.x, mci = pa.y, xri = pa.z, yci = pa.w;
     const int outb = kPackBias - pb.x;
+    const int adjb = (int)((uint32_t)pb.w >> 6);   // delta of swapping with the successor, + 2^25
     const uint32_t M = (uint32_t)c.M;
     // partners at or before the lane, or directly after it, need the masked path
     const bool diag = j0 <= tl * kWave + kWave;
@@ -230,7 +245,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     uint64_t best = kKeyNone;
     int j = j0;
     while (j < j1) {
-        const int r = c.posB[j].z >> 16;
+        const int r = (int)((uint32_t)c.posB[j].z >> 16);
         const int jend = min(j1, c.off[r + 1]);
         const bool t1 = (int)tabu[r * c.M + mi] > th;
         uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
@@ -239,7 +254,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     do {                                                                                       \
         const int d_ = outb - (b).x + (int)tc[xri + (a).y] + (int)tc[(a).x + yci]              \
                      + (int)tc[(a).z + mci] + (int)tc[mri + (a).w];                            \
-        const uint32_t p_ = ((uint32_t)d_ << 6) | (uint32_t)(b).w;                             \
+        const uint32_t p_ = ((uint32_t)d_ << 6) | ((uint32_t)(b).w & 63u);                     \
         const bool tb_ = t1 | ((int)tabu_ri[(b).z & 0xFFFF] > th);                             \
         mT = tb_ ? min(mT, p_) : mT;                                                           \
         mF = tb_ ? mF : min(mF, p_);                                                           \
@@ -257,16 +272,11 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
         } else {
             for (; j < jend; ++j) {
                 const int4 a = c.posA[j], b = c.posB[j];
-                int d;
-                if (j == i + 1 && ri == r) {
-                    // the lane's mission directly before the partner: P i j N -> P j i N
-                    d = kPackBias + (int)tc[xri + a.y] + (int)tc[a.x + mci] + (int)tc[mri + a.w]
-                      - ((int)tc[xri + mci] + (int)tc[mri + a.y] + (int)tc[a.x + a.w]);
-                } else {
-                    d = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
-                      + (int)tc[a.z + mci] + (int)tc[mri + a.w];
-                }
-                const uint32_t p = ((uint32_t)d << 6) | (uint32_t)b.w;
+                const int dg = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
+                             + (int)tc[a.z + mci] + (int)tc[mri + a.w];
+                // the lane's mission directly before the partner: delta from prep
+                const int d = (j == i + 1 && ri == r) ? adjb : dg;
+                const uint32_t p = ((uint32_t)d << 6) | ((uint32_t)b.w & 63u);
                 const bool tb = t1 | ((int)tabu_ri[b.z & 0xFFFF] > th);
                 const bool ok = j > i;
                 mT = (ok && tb) ? min(mT, p) : mT;
@@ -337,18 +347,18 @@ __device__ void dump_keys(const Ctx &c, const TE *tc, const int32_t *tabu, int t
     const int M = c.M;
     for (int i = tid; i < M; i += nthr) {
         const int4 pa = c.posA[i], pb = c.posB[i];
-        const int m = pb.z & 0xFFFF, ri = pb.z >> 16;
+        const int m = pb.z & 0xFFFF, ri = (int)((uint32_t)pb.z >> 16);
         const int rem = pb.y - pb.x;
         for (int G = 0; G < c.NG; ++G) {
             const int4 g = c.gap[G];
             const int d = rem + (int)tc[g.x + pa.y] + (int)tc[pa.x + g.y] - g.z;
             const bool noop = (unsigned)(G - (i + ri)) < 2u;
-            const bool tb = use_tabu && tabu[g.w * M + m] > t;
+            const bool tb = use_tabu && tabu[(g.w & 0xFFFF) * M + m] > t;
             keys[(uint32_t)m * c.NG + G] = noop ? kKeyNone : pack_key(tb && !(d < thr), d, (uint32_t)m * c.NG + G);
         }
         for (int j = i + 1; j < M; ++j) {
             const int4 a = c.posA[j], b = c.posB[j];
-            const int mj = b.z & 0xFFFF, rj = b.z >> 16;
+            const int mj = b.z & 0xFFFF, rj = (int)((uint32_t)b.z >> 16);
             int d;
             if (j == i + 1 && ri == rj)
                 d = (int)tc[pa.z + a.y] + (int)tc[a.x + pa.y] + (int)tc[pa.x + a.w]
@@ -366,7 +376,7 @@ __device__ void dump_keys(const Ctx &c, const TE *tc, const int32_t *tabu, int t
 // ---------------------------------------------------------------------------
 // LDS setup
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V, int chunk)
+__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V, int chunk, int Cs)
 {
     Ctx c;
     c.mrow = (int32_t *)(smem + ly.mrow);
@@ -382,11 +392,13 @@ __device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V,
     c.posB = (int4 *)(smem + ly.posB);
     c.gap = (int4 *)(smem + ly.gap);
     c.prank = (uint8_t *)(smem + ly.prank);
+    c.posC = nullptr;
     c.red = (uint64_t *)(smem + ly.red);
     c.M = M;
     c.V = V;
     c.NG = M + V;
     c.chunk = chunk;
+    c.Cs = Cs;
     c.R = (uint32_t)M * (uint32_t)(M + V);
     return c;
 }
@@ -498,7 +510,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), (int)sizeof(TB));
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, I.Cs);
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
@@ -605,7 +617,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (!is_swap) {
             const int m = (int)(idx / (uint32_t)c.NG);
             const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
-            const int v = c.gap[G].w;
+            const int v = c.gap[G].w & 0xFFFF;
             const int g = G - c.off[v] - v;
             const int s = c.pof[m];
             const int rs = c.rt[s];
@@ -739,17 +751,121 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.posB = B.posB;
     c.gap = B.gap;
     c.prank = B.prank;
+    c.posC = B.posC;
     c.red = red;
     c.M = I.M;
     c.V = I.V;
     c.NG = I.M + I.V;
     c.chunk = chunk;
+    c.Cs = I.Cs;
     c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
     return c;
 }
 
+// Eval of the global schedule: blocks of K consecutive route positions, dealt
+// round-robin to the workgroups.  For each block the four travel vectors its
+// missions' moves read -- the block column of the pickup and of the successor
+// (from the transposed block), the block row of the delivery and of the
+// predecessor -- and the tabu entries of its missions and vehicles are staged
+// in LDS; every thread then streams gap records (relocates) and later
+// positions (swaps) from HBM/L2 and scores them against the K missions.
 template <typename TE, typename TB>
-__device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, uint64_t *red)
+__device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
+                                const TB *tabu, char *smem, int K, int nrr, int wg, int nwg, int t,
+                                int thr, bool use_tabu)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int M = c.M, V = c.V, NG = c.NG, R = I.R, C = I.C, Rs = I.Rs;
+    const int per = 2 * R + 2 * C;
+    TE *vec = (TE *)smem;
+    TB *trow = (TB *)(smem + (((size_t)K * per * sizeof(TE) + 15) & ~(size_t)15));
+    TB *rrow = (TB *)((char *)trow + (((size_t)K * V * sizeof(TB) + 15) & ~(size_t)15));
+    const int th = use_tabu ? t : INT32_MAX;
+    const int nblk = (M + K - 1) / K;
+    uint64_t best = kKeyNone;
+    for (int blk = wg; blk < nblk; blk += nwg) {
+        const int i0 = blk * K;
+        const int kn = min(K, M - i0);
+        __syncthreads();
+        int rl[4] = {-1, -1, -1, -1};
+        int nd = 0;
+        for (int k = 0; k < kn; ++k) {
+            const int4 pa = c.posA[i0 + k];
+            const int4 pb = c.posB[i0 + k];
+            const int m = pb.z & 0xFFFF, r = (int)((uint32_t)pb.z >> 16);
+            TE *v = vec + k * per;
+            const TE *cp = tct + (size_t)pa.y * Rs, *cy = tct + (size_t)pa.w * Rs;
+            for (int q = tid; q < R; q += nthr) { v[q] = cp[q]; v[R + q] = cy[q]; }
+            const TE *rd = tc + pa.x, *rx = tc + pa.z;
+            for (int q = tid; q < C; q += nthr) { v[2 * R + q] = rd[q]; v[2 * R + C + q] = rx[q]; }
+            for (int u = tid; u < V; u += nthr) trow[k * V + u] = tabu[(size_t)u * M + m];
+            if (nd == 0 || rl[nd - 1] != r) rl[nd++] = r;
+        }
+        for (int q = 0; q < min(nd, nrr); ++q)
+            for (int m = tid; m < M; m += nthr) rrow[(size_t)q * M + m] = tabu[(size_t)rl[q] * M + m];
+        __syncthreads();
+        int km[4], kr[4], krem[4], kGi[4], kout[4], kadj[4], ksl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int kk = k < kn ? k : 0;
+            const int4 pb = c.posB[i0 + kk];
+            km[k] = pb.z & 0xFFFF;
+            kr[k] = (int)((uint32_t)pb.z >> 16);
+            krem[k] = pb.y - pb.x;
+            kGi[k] = i0 + kk + kr[k];
+            kout[k] = pb.x;
+            kadj[k] = (int)((uint32_t)pb.w >> 6) - kPackBias;
+            ksl[k] = -1;
+            for (int q = 0; q < min(nd, nrr); ++q)
+                if (rl[q] == kr[k]) ksl[k] = q;
+        }
+        const int ncol = NG + (M - i0 - 1);
+        for (int col = tid; col < ncol; col += nthr) {
+            if (col < NG) {
+                const int G = col;
+                const int4 g = c.gap[G];
+                const int gr = g.w & 0xFFFF, grow = (int)((uint32_t)g.w >> 16);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k < kn) {
+                        const TE *v = vec + k * per;
+                        const int d = krem[k] + (int)v[grow] + (int)v[2 * R + g.y] - g.z;
+                        const bool noop = (unsigned)(G - kGi[k]) < 2u;
+                        const bool blocked = (int)trow[k * V + gr] > th && !(d < thr);
+                        const uint64_t key = pack_key(blocked, d, (uint32_t)km[k] * (uint32_t)NG + (uint32_t)G);
+                        best = noop ? best : umin64(best, key);
+                    }
+                }
+            } else {
+                const int j = i0 + 1 + (col - NG);
+                const int4 a = c.posA[j], b = c.posB[j];
+                const int2 rc = c.posC[j];
+                const int mj = b.z & 0xFFFF, rj = (int)((uint32_t)b.z >> 16);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k < kn && j > i0 + k) {
+                        const TE *v = vec + k * per;
+                        int d;
+                        if (j == i0 + k + 1 && kr[k] == rj)
+                            d = kadj[k];
+                        else
+                            d = (int)v[2 * R + C + a.y] + (int)v[R + rc.x] + (int)v[rc.y] + (int)v[2 * R + a.w]
+                              - kout[k] - b.x;
+                        const int t2 = ksl[k] >= 0 ? (int)rrow[(size_t)ksl[k] * M + mj]
+                                                   : (int)tabu[(size_t)kr[k] * M + mj];
+                        const bool tb = (int)trow[k * V + rj] > th || t2 > th;
+                        const uint32_t lo = (uint32_t)min(km[k], mj), hi = (uint32_t)max(km[k], mj);
+                        best = umin64(best, pack_key(tb && !(d < thr), d, swap_index(c.R, (uint32_t)M, lo, hi)));
+                    }
+                }
+            }
+        }
+    }
+    return best;
+}
+
+template <typename TE, typename TB>
+__device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char *smem, uint64_t *red)
 {
     const InstDev &I = *J.inst;
     GlobalBufs &B = *J.gb;
@@ -803,7 +919,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, uint6
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_all<TE, TB>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
+        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, tabu, smem, J.gk, J.gnr, wg, nwg,
+                                         t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
         __syncthreads();
@@ -843,7 +960,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, uint6
         if (!is_swap) {
             const int m = (int)(idx / (uint32_t)c.NG);
             const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
-            const int v = c.gap[G].w;
+            const int v = c.gap[G].w & 0xFFFF;
             const int g = G - c.off[v] - v;
             const int s = c.pof[m];
             const int rs = c.rt[s];
@@ -943,8 +1060,12 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, uint6
 template <typename TE, typename TB>
 __global__ void __launch_bounds__(1024) k_search_global(const JobDev *job, Xchg *xs)
 {
-    __shared__ uint64_t red[128];
-    run_job_global<TE, TB>(*job, (int)blockIdx.x, (int)gridDim.x, xs, red);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const JobDev &J = *job;
+    const InstDev &I = *J.inst;
+    const uint32_t lds = global_lds_bytes(J.gk, J.gnr, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
+    uint64_t *red = (uint64_t *)(smem + lds - 1024);
+    run_job_global<TE, TB>(J, (int)blockIdx.x, (int)gridDim.x, xs, smem, red);
 }
 
 // One workgroup per job; jobs are taken from an atomic queue until exhausted.
@@ -987,7 +1108,7 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), 4);
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, I.Cs);
     TE *tc = (TE *)(smem + ly.tc);
     int32_t *tabu = (int32_t *)(smem + ly.tabu);
     load_instance<TE>(I, c, tc, tid, nthr);
@@ -1070,37 +1191,42 @@ hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int bl
 }
 
 template <typename TE, typename TB>
-static hipError_t coop_launch_global(const JobDev *job, Xchg *xs, int n_groups, int block, hipStream_t s)
+static hipError_t coop_launch_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+                                     uint32_t lds_bytes, hipStream_t s)
 {
+    hipError_t e = set_lds(k_search_global<TE, TB>, lds_bytes);
+    if (e != hipSuccess) return e;
     void *args[] = {(void *)&job, (void *)&xs};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search_global<TE, TB>),
-                                      dim3(n_groups), dim3(block), args, 0, s);
+                                      dim3(n_groups), dim3(block), args, lds_bytes, s);
 }
 
-hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block, int tb16,
-                                int esz16, hipStream_t s)
+hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s)
 {
-    if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(job, xs, n_groups, block, s);
-    if (esz16) return coop_launch_global<uint16_t, int32_t>(job, xs, n_groups, block, s);
-    if (tb16) return coop_launch_global<int32_t, uint16_t>(job, xs, n_groups, block, s);
-    return coop_launch_global<int32_t, int32_t>(job, xs, n_groups, block, s);
+    if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
+    if (esz16) return coop_launch_global<uint16_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
+    if (tb16) return coop_launch_global<int32_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
+    return coop_launch_global<int32_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
 }
 
 template <typename TE, typename TB>
-static int occupancy_global(int block)
+static int occupancy_global(int block, uint32_t lds_bytes)
 {
+    if (set_lds(k_search_global<TE, TB>, lds_bytes) != hipSuccess) return 0;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_global<TE, TB>, block, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_global<TE, TB>, block,
+                                                     lds_bytes) != hipSuccess)
         return 0;
     return per_cu * num_cus();
 }
 
-int max_groups_global(int block, int tb16, int esz16)
+int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16)
 {
-    if (esz16 && tb16) return occupancy_global<uint16_t, uint16_t>(block);
-    if (esz16) return occupancy_global<uint16_t, int32_t>(block);
-    if (tb16) return occupancy_global<int32_t, uint16_t>(block);
-    return occupancy_global<int32_t, int32_t>(block);
+    if (esz16 && tb16) return occupancy_global<uint16_t, uint16_t>(block, lds_bytes);
+    if (esz16) return occupancy_global<uint16_t, int32_t>(block, lds_bytes);
+    if (tb16) return occupancy_global<int32_t, uint16_t>(block, lds_bytes);
+    return occupancy_global<int32_t, int32_t>(block, lds_bytes);
 }
 
 template <typename TE, typename TB>

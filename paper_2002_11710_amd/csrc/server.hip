@@ -81,7 +81,7 @@ size_t request_bytes(const at_instance &in, const at_params &pr)
 {
     const size_t M = (size_t)in.n_missions, V = (size_t)in.n_vehicles;
     size_t b = al256(sizeof(InstDev)) + al256(sizeof(JobScal)) + al256(sizeof(SolveState));
-    b += inst_bytes(in);
+    b += inst_bytes(in, may_need_global(in, pr));
     b += al256(4 * M) + al256(4 * (V + 1)) + al256(4 * M * V);          // saved routes + tabu
     b += al256(4 * (V + 1)) + 2 * al256(4 * (M ? M : 1));                // best routes
     if (pr.trace) {
@@ -126,7 +126,8 @@ struct Server {
         r.dinst = (InstDev *)p; p += al256(sizeof(InstDev));
         r.scal = (JobScal *)p; p += al256(sizeof(JobScal));
         r.st = (SolveState *)p; p += al256(sizeof(SolveState));
-        carve_inst(r.host_inst, r.inst, p); p += inst_bytes(r.inst);
+        const bool with_t = may_need_global(r.inst, r.pr);
+        carve_inst(r.host_inst, r.inst, p, with_t); p += inst_bytes(r.inst, with_t);
         SolveState st{};
         st.seq = (int32_t *)p; p += al256(4 * M);
         st.off = (int32_t *)p; p += al256(4 * (V + 1));
