@@ -134,14 +134,19 @@ void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
         g.rof[k] = (uint16_t *)(base + o); o += a(2 * uM);
         g.off[k] = (int32_t *)(base + o); o += a(4 * (uV + 1));
     }
-    g.posA = (int4 *)(base + o); o += a(16 * uM);
-    g.posB = (int4 *)(base + o); o += a(16 * uM);
-    g.gap = (int4 *)(base + o); o += a(16 * (uM + uV));
-    g.posC = (int2 *)(base + o); o += a(8 * uM);
-    g.prank = (uint8_t *)(base + o); o += a(uM);
+    for (int k = 0; k < 2; ++k) {
+        g.posA[k] = (int4 *)(base + o); o += a(16 * uM);
+        g.posB[k] = (int4 *)(base + o); o += a(16 * uM);
+        g.gap[k] = (int4 *)(base + o); o += a(16 * (uM + uV));
+        g.posC[k] = (int2 *)(base + o); o += a(8 * uM);
+    }
     g.tabu = (void *)(base + o);
     g.cur = 0;
     g.pad = 0;
+    g.key[0] = g.key[1] = g.key[2] = kKeyNone;
+    g.cnt = 0;
+    g.abort = 0;
+    g.init_obj = 0;
 }
 
 struct WsPlan {
@@ -235,22 +240,21 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit) {
         if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
         h.kind = AT_SCHED_GLOBAL;
-        h.block = h.pr.block ? h.pr.block : 256;
+        // a requested block size above the schedule's limit applies to the other schedules only
+        h.block = h.pr.block ? std::min(h.pr.block, kGlobalBlock) : kGlobalBlock;
         if (!d.tct) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but its transposed block was not reserved");
-        // as many missions per block and staged vehicle rows as LDS holds
+        const int g = h.pr.n_groups ? h.pr.n_groups
+                                    : (int)std::max<int64_t>(1, std::min<int64_t>(num_cus(), h.slots / 16384));
+        // the most missions per block that LDS holds while every workgroup still gets a block
         h.gk = 0;
-        for (int K : {4, 2, 1}) {
-            for (int nrr : {2, 1, 0}) {
-                const uint32_t b = global_lds_bytes(K, nrr, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4);
-                if (b <= kLdsLimit) { h.gk = K; h.gnr = nrr; h.lds = b; break; }
-            }
-            if (h.gk) break;
+        for (int K = kGlobalKMax; K >= 1; K >>= 1) {
+            if (K > 1 && (d.M + K - 1) / K < g) continue;
+            const uint32_t b = global_lds_bytes(K, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4);
+            if (b <= kLdsLimit) { h.gk = K; h.lds = b; break; }
         }
         if (!h.gk) return fail(AT_ENOMEM, "instance too large: %d exit and %d entry locations do not fit the staged search", d.R, d.C);
         const int cap = max_groups_global(h.block, h.lds, h.tb16, h.esz16);
         if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
-        const int g = h.pr.n_groups ? h.pr.n_groups
-                                    : (int)std::max<int64_t>(1, std::min<int64_t>(num_cus(), h.slots / 16384));
         h.groups = std::max(1, std::min(g, cap));
         return AT_OK;
     }
@@ -300,7 +304,8 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.st = nullptr;
     j.gb = h.gstate;
     j.gk = h.gk;
-    j.gnr = h.gnr;
+    j.g0 = h.g0;
+    j.ng = h.groups;
     return AT_OK;
 }
 
@@ -400,18 +405,31 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         for (hipEvent_t ev : joins) if (ev) (void)hipEventDestroy(ev);
         if (rc) return rc;
     }
-    for (; k < n; ++k) {
+    while (k < n) {
         const JobHost &hf = jobs[(size_t)order[(size_t)k]];
+        if (hf.kind == AT_SCHED_GLOBAL) {
+            // one cooperative launch for the jobs assign_groups put together
+            int e1 = k, groups = 0;
+            uint32_t lds = 0;
+            while (e1 < n && jobs[(size_t)order[(size_t)e1]].kind == AT_SCHED_GLOBAL &&
+                   jobs[(size_t)order[(size_t)e1]].launch == hf.launch) {
+                const JobHost &h = jobs[(size_t)order[(size_t)e1]];
+                groups = std::max(groups, h.g0 + h.groups);
+                lds = std::max(lds, h.lds);
+                ++e1;
+            }
+            if ((e = launch_search_global(dj + k, e1 - k, groups, hf.block, lds, hf.tb16, hf.esz16, s)) != hipSuccess)
+                return hip_fail(e, "cooperative search launch");
+            k = e1;
+            continue;
+        }
         if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
         if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
-        if (hf.kind == AT_SCHED_MULTI &&
-            (e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups, s)) != hipSuccess)
+        if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups, s)) != hipSuccess)
             return hip_fail(e, "reset exchange");
-        if (hf.kind == AT_SCHED_MULTI)
-            e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
-        else
-            e = launch_search_global(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
+        e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
         if (e != hipSuccess) return hip_fail(e, "cooperative search launch");
+        ++k;
     }
     return AT_OK;
 }
@@ -428,13 +446,55 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
         const JobHost &x = jobs[(size_t)a], &y = jobs[(size_t)b];
         const int cx = x.kind == AT_SCHED_WG ? 0 : x.kind, cy = y.kind == AT_SCHED_WG ? 0 : y.kind;
         if (cx != cy) return cx < cy;
-        if (x.kind == AT_SCHED_WG) {
+        if (x.kind == AT_SCHED_WG || x.kind == AT_SCHED_GLOBAL) {
             const int kx = (x.esz16 * 2 + x.tb16) * 4096 + x.block, ky = (y.esz16 * 2 + y.tb16) * 4096 + y.block;
             if (kx != ky) return kx > ky;
         }
         return x.slots > y.slots;
     });
     return order;
+}
+
+// Split the global-schedule jobs (consecutive in `order`, grouped by class)
+// into cooperative launches and give each job a range of its launch's
+// workgroups: as many as it asked for when they all fit the co-resident
+// limit, else shares proportional to the request (at least one each).
+int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
+{
+    const int n = (int)order.size();
+    int k = 0, launch = 0;
+    while (k < n && jobs[(size_t)order[(size_t)k]].kind != AT_SCHED_GLOBAL) ++k;
+    while (k < n && jobs[(size_t)order[(size_t)k]].kind == AT_SCHED_GLOBAL) {
+        const JobHost &hf = jobs[(size_t)order[(size_t)k]];
+        int e = k;
+        uint32_t lds = 0;
+        while (e < n) {
+            const JobHost &h = jobs[(size_t)order[(size_t)e]];
+            if (h.kind != AT_SCHED_GLOBAL || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block) break;
+            lds = std::max(lds, h.lds);
+            ++e;
+        }
+        const int cap = max_groups_global(hf.block, lds, hf.tb16, hf.esz16);
+        if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
+        for (int a = k; a < e; a += cap, ++launch) {
+            const int b = std::min(e, a + cap);
+            int64_t want = 0;
+            for (int q = a; q < b; ++q) want += jobs[(size_t)order[(size_t)q]].groups;
+            int g0 = 0;
+            for (int q = a; q < b; ++q) {
+                JobHost &h = jobs[(size_t)order[(size_t)q]];
+                int g = h.groups;
+                if (want > cap) g = std::max<int>(1, (int)((int64_t)h.groups * cap / want));
+                g = std::min(g, cap - g0 - (b - q - 1));   // leave one for each later job
+                h.groups = std::max(1, g);
+                h.g0 = g0;
+                h.launch = launch;
+                g0 += h.groups;
+            }
+        }
+        k = e;
+    }
+    return AT_OK;
 }
 
 struct EventPair {
@@ -466,6 +526,7 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
     int rc = upload_gstates(jobs, ih, s);
     if (rc) return rc;
     const std::vector<int> order = order_jobs(jobs);
+    if ((rc = assign_groups(jobs, order)) != AT_OK) return rc;
     std::vector<JobDev> hj((size_t)n);
     for (int k = 0; k < n; ++k) {
         const JobHost &h = jobs[(size_t)order[(size_t)k]];

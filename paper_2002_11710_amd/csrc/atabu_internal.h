@@ -87,14 +87,20 @@ struct SolveState {
 // are double-buffered so that every workgroup can write the next iteration's
 // routes while others still read the current ones.
 struct GlobalBufs {
+    // routes and the records built from them, double-buffered: an iteration reads
+    // one parity and writes the next iteration's routes and records to the other
     uint16_t *seq[2], *rt[2], *pof[2], *rof[2];
     int32_t *off[2];
-    int4 *posA, *posB, *gap;
-    int2 *posC;                       // per position: exit row of its delivery, of its predecessor
-    uint8_t *prank;
+    int4 *posA[2], *posB[2], *gap[2];
+    int2 *posC[2];                    // per position: exit row of its delivery, of its predecessor
     void *tabu;
-    int32_t cur;                      // which buffer holds the current routes
+    int32_t cur;                      // which parity holds the current routes
     int32_t pad;
+    // exchange of the solve's workgroups (cleared before every launch), on its own cache lines
+    alignas(128) uint64_t key[3];     // argmin slots, by iteration mod 3
+    uint32_t cnt;                     // barrier arrivals (monotone within a launch)
+    uint32_t abort;                   // set by a workgroup whose wait ran out
+    int64_t init_obj;                 // greedy objective, published by workgroup 0
 };
 
 struct JobDev {
@@ -105,7 +111,7 @@ struct JobDev {
     int32_t tb16;                     // tabu entries stored as uint16 in LDS
     int32_t chunk;                    // columns per work unit
     int32_t gk;                       // global schedule: missions staged per block
-    int32_t gnr;                      // global schedule: vehicle tabu rows staged per block
+    int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
     uint64_t seed;
     int32_t *out_off, *out_seq, *out_of;
     uint32_t *tr_move;
@@ -189,7 +195,7 @@ __host__ __device__ inline uint64_t global_state_bytes(int M, int V, int tbsz)
 {
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V, NG = uM + uV;
     auto a = [](uint64_t x) { return (x + 255u) & ~(uint64_t)255u; };
-    return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * a(16 * uM) + a(16 * NG) + a(8 * uM) + a(uM)
+    return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * (2 * a(16 * uM) + a(16 * NG) + a(8 * uM))
          + a((uint64_t)tbsz * uM * uV);
 }
 
@@ -203,19 +209,31 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
-hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
+// Missions staged per block by the global schedule's eval, at most.
+constexpr int kGlobalKMax = 8;
+// Threads per workgroup of the global schedule, at most.
+constexpr int kGlobalBlock = 512;
+
+// Staged lengths (elements) of the travel vectors of the global schedule's
+// eval: a column of the block (R exit rows) in whole 16-byte chunks, a row
+// (C entry columns) in whole 8-byte pieces.  The transposed block's row stride
+// is the column length, so its rows are 16-byte aligned.
+__host__ __device__ inline int staged_rows(int R, int esz) { const int q = 16 / esz; return (R + q - 1) / q * q; }
+__host__ __device__ inline int staged_cols(int C, int esz) { const int q = 8 / esz; return (C + q - 1) / q * q; }
+
 // LDS bytes of the global schedule's mission-major eval: K missions' four
-// travel vectors, their tabu columns and nrr vehicle tabu rows.
-__host__ __device__ inline uint32_t global_lds_bytes(int K, int nrr, int R, int C, int M, int V,
-                                                     int esz, int tbsz)
+// travel vectors and tabu columns, one tabu bit row (M bits) per vehicle of the
+// block (at most K), then 2 KiB of reduction slots and per-block tables.
+__host__ __device__ inline uint32_t global_lds_bytes(int K, int R, int C, int M, int V, int esz, int tbsz)
 {
-    const uint64_t vec = (uint64_t)K * (2 * (uint64_t)R + 2 * (uint64_t)C) * (uint64_t)esz;
+    const uint64_t Re = (uint64_t)staged_rows(R, esz), Ce = (uint64_t)staged_cols(C, esz);
+    const uint64_t vec = (uint64_t)K * (2 * Re + 2 * Ce) * (uint64_t)esz;
     const uint64_t tk = (uint64_t)K * (uint64_t)V * (uint64_t)tbsz;
-    const uint64_t rr = (uint64_t)nrr * (uint64_t)M * (uint64_t)tbsz;
-    const uint64_t tot = al16((uint32_t)0) + ((vec + 15) & ~15ull) + ((tk + 15) & ~15ull)
-                       + ((rr + 15) & ~15ull) + 1024;
+    const uint64_t rb = (uint64_t)K * (((uint64_t)M + 31) / 32) * 4;
+    const uint64_t tot = ((vec + 15) & ~15ull) + ((tk + 15) & ~15ull) + ((rb + 15) & ~15ull) + 2048;
     return tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
 }
 hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_t *seq,

@@ -27,7 +27,8 @@ struct JobHost {
     uint32_t lds = 0;
     int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
-    int gk = 0, gnr = 0;              // global schedule: staged missions / vehicle rows per block
+    int gk = 0;                       // global schedule: missions staged per block
+    int g0 = 0, launch = 0;           // global schedule: first workgroup, launch index (assign_groups)
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
 };
 
@@ -48,5 +49,6 @@ int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> 
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
                 Xchg *xs, hipStream_t s);
 std::vector<int> order_jobs(const std::vector<JobHost> &jobs);
+int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order);
 
 }  // namespace at

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     const int R = I.R, C = I.C;
     const int esz = s_max <= 65535 ? 2 : 4;
     const int Cs = compact_stride(C, esz);
-    const int Rs = compact_stride(R, esz);
+    const int Rs = staged_rows(R, esz);
     if ((int64_t)R * Cs * esz > I.tc_cap || (I.tct && (int64_t)C * Rs * esz > I.tc_cap)) {
         if (tid == 0) I.status = AT_ENOMEM;
         return;

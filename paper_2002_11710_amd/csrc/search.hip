@@ -706,22 +706,27 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 }
 
 // ---------------------------------------------------------------------------
-// global schedule: state in HBM, gridDim.x workgroups per solve, three grid
-// barriers per iteration (after prep, the argmin exchange, after apply)
+// global schedule: state in HBM.  Each solve runs on its own range of the
+// launch's workgroups, which meet at two barriers per iteration: after the
+// argmin exchange, and after the move is applied and the next iteration's
+// records are written.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool grid_barrier(Xchg *xs, int nwg, uint32_t &nb, uint64_t *flag)
+constexpr uint64_t kBarrierTicks = 20ull * 100000000ull;   // 20 s of the 100 MHz wall clock
+
+__device__ __forceinline__ bool job_barrier(GlobalBufs &B, int nwg, uint32_t &nb, uint64_t *flag)
 {
     __syncthreads();
     ++nb;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&xs->cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&B.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = nb * (uint32_t)nwg;
-        uint32_t spins = 0, ab = 0;
-        while (__hip_atomic_load(&xs->cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            ab = __hip_atomic_load(&xs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        uint32_t ab = 0;
+        while (__hip_atomic_load(&B.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            ab = __hip_atomic_load(&B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (ab) break;
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&xs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (wall_clock64() - t0 > kBarrierTicks) {
+                __hip_atomic_store(&B.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ab = 1;
                 break;
             }
@@ -734,8 +739,8 @@ __device__ __forceinline__ bool grid_barrier(Xchg *xs, int nwg, uint32_t &nb, ui
     return *flag == 0;
 }
 
-__device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B, int p,
-                                          uint64_t *red, int chunk)
+// Routes of parity p (p = 0, 1: double-buffered) and the records built from them.
+__device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B, int p, uint64_t *red)
 {
     Ctx c;
     c.mrow = I.mrow;
@@ -747,116 +752,363 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.rt = B.rt[p];
     c.rof = B.rof[p];
     c.pof = B.pof[p];
-    c.posA = B.posA;
-    c.posB = B.posB;
-    c.gap = B.gap;
-    c.prank = B.prank;
-    c.posC = B.posC;
+    c.posA = B.posA[p];
+    c.posB = B.posB[p];
+    c.gap = B.gap[p];
+    c.posC = B.posC[p];
+    c.prank = nullptr;
     c.red = red;
     c.M = I.M;
     c.V = I.V;
     c.NG = I.M + I.V;
-    c.chunk = chunk;
+    c.chunk = 0;
     c.Cs = I.Cs;
     c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
     return c;
 }
 
-// Eval of the global schedule: blocks of K consecutive route positions, dealt
-// round-robin to the workgroups.  For each block the four travel vectors its
-// missions' moves read -- the block column of the pickup and of the successor
-// (from the transposed block), the block row of the delivery and of the
-// predecessor -- and the tabu entries of its missions and vehicles are staged
-// in LDS; every thread then streams gap records (relocates) and later
-// positions (swaps) from HBM/L2 and scores them against the K missions.
+// The move an iteration applies, decoded once by every thread.
+struct GMove {
+    int kind;                  // 0 none, 1 relocate, 2 swap
+    int m, v, q, lo, hi, dir;  // relocate: mission, target vehicle, final position, shifted range and shift
+    int rs;                    // relocate: the mission's vehicle before the move
+    int s1, s2, m1, m2;        // swap: the two positions and their missions
+};
+
+// Mission, vehicle and route offsets of the routes after `mv`, read from the
+// routes before it (o): the missions between the old and new position of a
+// relocated mission shift by one place; a swap exchanges two entries.
+__device__ __forceinline__ int next_seq(const Ctx &o, const GMove &mv, int k)
+{
+    if (mv.kind == 1) {
+        if (k == mv.q) return mv.m;
+        return o.seq[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
+    }
+    if (mv.kind == 2) {
+        if (k == mv.s1) return mv.m2;
+        if (k == mv.s2) return mv.m1;
+    }
+    return o.seq[k];
+}
+
+__device__ __forceinline__ int next_rt(const Ctx &o, const GMove &mv, int k)
+{
+    if (mv.kind == 1) {
+        if (k == mv.q) return mv.v;
+        return o.rt[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
+    }
+    return o.rt[k];
+}
+
+__device__ __forceinline__ int next_off(const Ctx &o, const GMove &mv, int r)
+{
+    int x = o.off[r];
+    if (mv.kind == 1) {
+        if (mv.v > mv.rs && r > mv.rs && r <= mv.v) x -= 1;
+        if (mv.v < mv.rs && r > mv.v && r <= mv.rs) x += 1;
+    }
+    return x;
+}
+
+// Apply `mv` to the routes of `o` and build the records of the result (the
+// per-position and per-gap records of prep, without chunk ranks, plus the row
+// indices of each position's own exit and its predecessor's) into `n`; with
+// write_routes the routes after the move are written to `n` as well.  Every
+// value comes from `o` and the instance, so the workgroups of a solve need no
+// barrier between applying the move and building the records.
+template <typename TE>
+__device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE *tc, bool write_routes,
+                          int tid, int nthr)
+{
+    const uint32_t Cs = (uint32_t)o.Cs;
+    const int M = o.M, V = o.V;
+    for (int i = tid; i < M; i += nthr) {
+        const int m = next_seq(o, mv, i), r = next_rt(o, mv, i);
+        const int sp = i > 0 ? next_seq(o, mv, i - 1) : 0;
+        const int sn = i + 1 < M ? next_seq(o, mv, i + 1) : 0;
+        const int sn2 = i + 2 < M ? next_seq(o, mv, i + 2) : 0;
+        const int o0 = next_off(o, mv, r), o1 = next_off(o, mv, r + 1);
+        const bool first = i == o0, last = i + 1 == o1;
+        const int x = first ? o.vrow[r] : o.mrow[sp];
+        const int y = last ? o.vcol[r] : o.mcol[sn];
+        const int mc = o.mcol[m], mr = o.mrow[m];
+        const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
+        int adj = 0;
+        if (!last) {
+            // swapping m with its successor in the same route: P m n N -> P n m N
+            const int y2 = (i + 2 == o1) ? o.vcol[r] : o.mcol[sn2];
+            const int mrn = o.mrow[sn];
+            adj = l + (int)tc[mrn + mc] + (int)tc[mr + y2] - a - bb - (int)tc[mrn + y2];
+        }
+        n.posA[i] = make_int4(mr, mc, x, y);
+        n.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
+                              (int)((uint32_t)(adj + kPackBias) << 6));
+        n.gap[i + r] = make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        n.posC[i] = make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs));
+        if (write_routes) {
+            n.seq[i] = (uint16_t)m;
+            n.rt[i] = (uint16_t)r;
+            n.pof[m] = (uint16_t)i;
+            n.rof[m] = (uint16_t)r;
+        }
+    }
+    for (int r = tid; r <= V; r += nthr) {
+        const int o0 = next_off(o, mv, r);
+        if (write_routes) n.off[r] = o0;
+        if (r == V) continue;
+        // the gap after the route's last mission
+        const int e = next_off(o, mv, r + 1);
+        const int x = (o0 == e) ? o.vrow[r] : o.mrow[next_seq(o, mv, e - 1)];
+        n.gap[e + r] = make_int4(x, o.vcol[r], (int)tc[x + o.vcol[r]],
+                                 (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+    }
+}
+
+// Eval of the global schedule: blocks of K (at most kGlobalKMax) consecutive
+// route positions, dealt round-robin to the solve's workgroups.  For each
+// block the four travel vectors its missions' moves read -- the block column
+// of the pickup and of the successor (from the transposed block), the block
+// row of the delivery and of the predecessor -- the missions' tabu columns and
+// the tabu rows of the block's vehicles (one bit per mission: active or not)
+// are staged in LDS, each thread's loads issued before its first store.  Every
+// thread then streams gap records (relocates) and later positions (swaps) from
+// HBM/L2, UR or US in flight, and scores each against the K missions; inside
+// one (mission, round) the keys are 32-bit -- blocked bit, delta + 2^25, then
+// the column's rank -- and their minimum joins the 64-bit key of the lane.
+// Rounds that hold a no-op column, the mission's own neighbours or the tail
+// take a checked path; all others skip the checks.  `tab` is a 1 KiB LDS table:
+// 32 source pointers, then two int4 per mission, then the block's vehicles.
 template <typename TE, typename TB>
 __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
-                                const TB *tabu, char *smem, int K, int nrr, int wg, int nwg, int t,
-                                int thr, bool use_tabu)
+                                const TB *tabu, char *smem, uint64_t *tab, int K, int wg, int nwg,
+                                int t, int thr, bool use_tabu)
 {
+    constexpr int UR = 8, US = 4, UL = 8;      // relocate, swap and staging loads in flight
+    constexpr int ES = (int)sizeof(TE);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int M = c.M, V = c.V, NG = c.NG, R = I.R, C = I.C, Rs = I.Rs;
-    const int per = 2 * R + 2 * C;
+    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
+    const int M = c.M, V = c.V, NG = c.NG, Rs = I.Rs;
+    const int Re = staged_rows(I.R, ES), Ce = staged_cols(I.C, ES);
+    const int R16 = Re * ES / 16;              // 16-byte chunks of a staged column
+    const int Cw = (I.C * ES + 3) / 4;         // 4-byte words of a staged row
+    const int per = 2 * Re + 2 * Ce;
+    const int Wm = (M + 31) >> 5;
     TE *vec = (TE *)smem;
     TB *trow = (TB *)(smem + (((size_t)K * per * sizeof(TE) + 15) & ~(size_t)15));
-    TB *rrow = (TB *)((char *)trow + (((size_t)K * V * sizeof(TB) + 15) & ~(size_t)15));
+    uint32_t *rbits = (uint32_t *)((char *)trow + (((size_t)K * V * sizeof(TB) + 15) & ~(size_t)15));
+    int4 *mi = (int4 *)(tab + 4 * kGlobalKMax);   // {m | r << 16, rem, own gap, out}
+    int4 *mi2 = mi + kGlobalKMax;                 // {adjacent-swap delta, vehicle slot, -, -}
+    int *rl = (int *)(mi2 + kGlobalKMax);         // the block's vehicles; their count at rl[kGlobalKMax]
     const int th = use_tabu ? t : INT32_MAX;
     const int nblk = (M + K - 1) / K;
     uint64_t best = kKeyNone;
     for (int blk = wg; blk < nblk; blk += nwg) {
         const int i0 = blk * K;
         const int kn = min(K, M - i0);
-        __syncthreads();
-        int rl[4] = {-1, -1, -1, -1};
-        int nd = 0;
-        for (int k = 0; k < kn; ++k) {
+        __syncthreads();   // the previous block's LDS reads are done
+        if (tid < kn) {
+            const int4 pb = c.posB[i0 + tid];
+            const int r = (int)((uint32_t)pb.z >> 16);
+            mi[tid] = make_int4(pb.z, pb.y - pb.x, i0 + tid + r, pb.x);
+            mi2[tid] = make_int4((int)((uint32_t)pb.w >> 6) - kPackBias, 0, 0, 0);
+        } else if (tid >= kWave && tid < kWave + 4 * kn) {
+            const int q = tid - kWave, k = q >> 2, ty = q & 3;
             const int4 pa = c.posA[i0 + k];
-            const int4 pb = c.posB[i0 + k];
-            const int m = pb.z & 0xFFFF, r = (int)((uint32_t)pb.z >> 16);
-            TE *v = vec + k * per;
-            const TE *cp = tct + (size_t)pa.y * Rs, *cy = tct + (size_t)pa.w * Rs;
-            for (int q = tid; q < R; q += nthr) { v[q] = cp[q]; v[R + q] = cy[q]; }
-            const TE *rd = tc + pa.x, *rx = tc + pa.z;
-            for (int q = tid; q < C; q += nthr) { v[2 * R + q] = rd[q]; v[2 * R + C + q] = rx[q]; }
-            for (int u = tid; u < V; u += nthr) trow[k * V + u] = tabu[(size_t)u * M + m];
-            if (nd == 0 || rl[nd - 1] != r) rl[nd++] = r;
+            const TE *src = ty == 0 ? tct + (size_t)pa.y * Rs
+                          : ty == 1 ? tct + (size_t)pa.w * Rs
+                          : ty == 2 ? tc + pa.x : tc + pa.z;
+            tab[q] = (uint64_t)(uintptr_t)src;
         }
-        for (int q = 0; q < min(nd, nrr); ++q)
-            for (int m = tid; m < M; m += nthr) rrow[(size_t)q * M + m] = tabu[(size_t)rl[q] * M + m];
         __syncthreads();
-        int km[4], kr[4], krem[4], kGi[4], kout[4], kadj[4], ksl[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int kk = k < kn ? k : 0;
-            const int4 pb = c.posB[i0 + kk];
-            km[k] = pb.z & 0xFFFF;
-            kr[k] = (int)((uint32_t)pb.z >> 16);
-            krem[k] = pb.y - pb.x;
-            kGi[k] = i0 + kk + kr[k];
-            kout[k] = pb.x;
-            kadj[k] = (int)((uint32_t)pb.w >> 6) - kPackBias;
-            ksl[k] = -1;
-            for (int q = 0; q < min(nd, nrr); ++q)
-                if (rl[q] == kr[k]) ksl[k] = q;
+        if (tid < kn) {
+            // the block's vehicles in order (positions are route-ordered) and each mission's slot
+            const int r = (int)((uint32_t)mi[tid].x >> 16);
+            int slot = 0;
+            for (int k = 1; k <= tid; ++k) slot += ((uint32_t)mi[k].x >> 16) != ((uint32_t)mi[k - 1].x >> 16) ? 1 : 0;
+            mi2[tid].y = slot;
+            if (tid == 0 || ((uint32_t)mi[tid - 1].x >> 16) != (uint32_t)r) rl[slot] = r;
+            if (tid == kn - 1) rl[kGlobalKMax] = slot + 1;
         }
-        const int ncol = NG + (M - i0 - 1);
-        for (int col = tid; col < ncol; col += nthr) {
-            if (col < NG) {
-                const int G = col;
-                const int4 g = c.gap[G];
-                const int gr = g.w & 0xFFFF, grow = (int)((uint32_t)g.w >> 16);
+        __syncthreads();
+        const int nd = rl[kGlobalKMax];
+        // one pass of loads: the pickup and successor columns (16-byte chunks of the
+        // transposed block), the delivery and predecessor rows (4-byte words of the
+        // block), the missions' tabu columns (kn x V entries)
+        {
+            const int nA = 2 * kn * R16, nB = nA + 2 * kn * Cw, nC = nB + kn * V;
+            char *lds = (char *)vec;
+            for (int b0 = tid; b0 < nC; b0 += UL * nthr) {
+                uint4 val[UL];
+                int dst[UL], kind[UL];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (k < kn) {
-                        const TE *v = vec + k * per;
-                        const int d = krem[k] + (int)v[grow] + (int)v[2 * R + g.y] - g.z;
-                        const bool noop = (unsigned)(G - kGi[k]) < 2u;
-                        const bool blocked = (int)trow[k * V + gr] > th && !(d < thr);
-                        const uint64_t key = pack_key(blocked, d, (uint32_t)km[k] * (uint32_t)NG + (uint32_t)G);
-                        best = noop ? best : umin64(best, key);
+                for (int u = 0; u < UL; ++u) {
+                    const int it = b0 + u * nthr;
+                    kind[u] = it < nA ? 0 : it < nB ? 1 : it < nC ? 2 : 3;
+                    dst[u] = 0;
+                    val[u] = make_uint4(0u, 0u, 0u, 0u);
+                    if (kind[u] == 0) {
+                        const int v = it / R16, o = it - v * R16;
+                        const int k = v >> 1, ty = v & 1;
+                        val[u] = ((const uint4 *)(uintptr_t)tab[4 * k + ty])[o];
+                        dst[u] = (k * per + ty * Re) * ES + 16 * o;
+                    } else if (kind[u] == 1) {
+                        const int e = it - nA, v = e / Cw, o = e - v * Cw;
+                        const int k = v >> 1, ty = v & 1;
+                        val[u].x = ((const uint32_t *)(uintptr_t)tab[4 * k + 2 + ty])[o];
+                        dst[u] = (k * per + 2 * Re + ty * Ce) * ES + 4 * o;
+                    } else if (kind[u] == 2) {
+                        const int e = it - nB, k = e / V, r = e - k * V;
+                        val[u].x = (uint32_t)tabu[(size_t)r * M + (mi[k].x & 0xFFFF)];
+                        dst[u] = e;
                     }
                 }
-            } else {
-                const int j = i0 + 1 + (col - NG);
-                const int4 a = c.posA[j], b = c.posB[j];
-                const int2 rc = c.posC[j];
-                const int mj = b.z & 0xFFFF, rj = (int)((uint32_t)b.z >> 16);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (k < kn && j > i0 + k) {
-                        const TE *v = vec + k * per;
-                        int d;
-                        if (j == i0 + k + 1 && kr[k] == rj)
-                            d = kadj[k];
-                        else
-                            d = (int)v[2 * R + C + a.y] + (int)v[R + rc.x] + (int)v[rc.y] + (int)v[2 * R + a.w]
-                              - kout[k] - b.x;
-                        const int t2 = ksl[k] >= 0 ? (int)rrow[(size_t)ksl[k] * M + mj]
-                                                   : (int)tabu[(size_t)kr[k] * M + mj];
-                        const bool tb = (int)trow[k * V + rj] > th || t2 > th;
-                        const uint32_t lo = (uint32_t)min(km[k], mj), hi = (uint32_t)max(km[k], mj);
-                        best = umin64(best, pack_key(tb && !(d < thr), d, swap_index(c.R, (uint32_t)M, lo, hi)));
+                for (int u = 0; u < UL; ++u) {
+                    if (kind[u] == 0) *(uint4 *)(lds + dst[u]) = val[u];
+                    else if (kind[u] == 1) *(uint32_t *)(lds + dst[u]) = val[u].x;
+                    else if (kind[u] == 2) trow[dst[u]] = (TB)val[u].x;
+                }
+            }
+        }
+        // the block's vehicles' tabu rows as bits: one 64-mission chunk per wave
+        {
+            const int Mc = (M + 63) >> 6, nch = nd * Mc;
+            for (int c0 = wave; c0 < nch; c0 += UL * nwaves) {
+                TB val[UL];
+#pragma unroll
+                for (int u = 0; u < UL; ++u) {
+                    const int ch = c0 + u * nwaves;
+                    const int q = ch / Mc, m = (ch - q * Mc) * 64 + lane;
+                    val[u] = (ch < nch && m < M) ? tabu[(size_t)rl[q] * M + m] : (TB)0;
+                }
+#pragma unroll
+                for (int u = 0; u < UL; ++u) {
+                    const int ch = c0 + u * nwaves;
+                    if (ch >= nch) break;   // uniform across the wave
+                    const int q = ch / Mc, cm = ch - q * Mc;
+                    const uint64_t bits = __ballot((int)val[u] > th && cm * 64 + lane < M);
+                    if (lane == 0) {
+                        rbits[q * Wm + 2 * cm] = (uint32_t)bits;
+                        if (2 * cm + 1 < Wm) rbits[q * Wm + 2 * cm + 1] = (uint32_t)(bits >> 32);
                     }
+                }
+            }
+        }
+        __syncthreads();
+        // relocates: every gap against the block's missions
+        for (int b0 = tid; b0 < NG; b0 += UR * nthr) {
+            const int rb = b0 - tid;                      // first column of the round
+            const bool tail = rb + UR * nthr > NG;
+            int4 g[UR];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int G = b0 + u * nthr;
+                g[u] = c.gap[G < NG ? G : 0];
+            }
+            for (int k = 0; k < kn; ++k) {
+                const int4 q = mi[k];
+                const TE *v = vec + k * per;
+                const TB *tr = trow + k * V;
+                uint32_t mn = 0xFFFFFFFFu;
+                if (!tail && (q.z + 1 < rb || q.z >= rb + UR * nthr)) {
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
+                        const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
+                        const bool blk = (int)tr[gr] > th && !(d < thr);
+                        const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
+                        mn = min(mn, key);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        const int G = b0 + u * nthr;
+                        const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
+                        const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
+                        const bool blk = (int)tr[gr] > th && !(d < thr);
+                        const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
+                        const bool skip = G >= NG || (unsigned)(G - q.z) < 2u;
+                        mn = skip ? mn : min(mn, key);
+                    }
+                }
+                if (mn != 0xFFFFFFFFu) {
+                    const int G = b0 + (int)(mn & 31u) * nthr;
+                    const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
+                    best = umin64(best, pack_key((mn >> 31) != 0, d,
+                                                 (uint32_t)(q.x & 0xFFFF) * (uint32_t)NG + (uint32_t)G));
+                }
+            }
+        }
+        // swaps: every later position against the block's missions
+        const int j0 = i0 + 1;
+        for (int b0 = j0 + tid; b0 < M; b0 += US * nthr) {
+            const int rb = b0 - tid;
+            const bool tail = rb + US * nthr > M;
+            int4 a[US], b[US];
+            int2 rc[US];
+            int mj[US], rk[US];
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                const int j = b0 + u * nthr < M ? b0 + u * nthr : j0;
+                a[u] = c.posA[j];
+                b[u] = c.posB[j];
+                rc[u] = c.posC[j];
+            }
+            // rank of each partner's mission among the lane's partners of the round
+            // (swap indices of one mission grow with the partner's mission)
+#pragma unroll
+            for (int u = 0; u < US; ++u)
+                mj[u] = b0 + u * nthr < M ? (b[u].z & 0xFFFF) : 0x10000 + u;
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                int r = 0;
+#pragma unroll
+                for (int w = 0; w < US; ++w) r += (w != u && mj[w] < mj[u]) ? 1 : 0;
+                rk[u] = r;
+            }
+            for (int k = 0; k < kn; ++k) {
+                const int4 q = mi[k];
+                const int4 q2 = mi2[k];
+                const int mk = q.x & 0xFFFF, rkk = (int)((uint32_t)q.x >> 16);
+                const int jk = i0 + k;
+                const TE *v = vec + k * per;
+                const TB *tr = trow + k * V;
+                const uint32_t *rbit = rbits + q2.y * Wm;
+                uint32_t mn = 0xFFFFFFFFu;
+                if (!tail && rb > jk + 1) {
+#pragma unroll
+                    for (int u = 0; u < US; ++u) {
+                        const int rj = (int)((uint32_t)b[u].z >> 16);
+                        const int d = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
+                                    + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
+                        const bool tb = ((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0);
+                        const uint32_t key = ((tb && !(d < thr)) ? 0x80000000u : 0u)
+                                           | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
+                        mn = min(mn, key);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < US; ++u) {
+                        const int j = b0 + u * nthr;
+                        const int rj = (int)((uint32_t)b[u].z >> 16);
+                        const int m2 = mj[u] & 0xFFFF;
+                        const int dg = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
+                                     + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
+                        const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
+                        const bool tb = ((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0);
+                        const uint32_t key = ((tb && !(d < thr)) ? 0x80000000u : 0u)
+                                           | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
+                        mn = (j >= M || j <= jk) ? mn : min(mn, key);
+                    }
+                }
+                if (mn != 0xFFFFFFFFu) {
+                    const int r = (int)(mn & 31u);
+                    int mw = mj[0];
+#pragma unroll
+                    for (int u = 1; u < US; ++u) mw = rk[u] == r ? mj[u] : mw;
+                    const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
+                    const uint32_t lo = (uint32_t)min(mk, mw), hi = (uint32_t)max(mk, mw);
+                    best = umin64(best, pack_key((mn >> 31) != 0, d, swap_index(c.R, (uint32_t)M, lo, hi)));
                 }
             }
         }
@@ -865,7 +1117,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 }
 
 template <typename TE, typename TB>
-__device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char *smem, uint64_t *red)
+__device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uint64_t *red)
 {
     const InstDev &I = *J.inst;
     GlobalBufs &B = *J.gb;
@@ -892,34 +1144,38 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
     } else {
         p = 0;
         if (wg == 0) {
-            const Ctx c0 = global_ctx(I, B, 0, red, J.chunk);
+            const Ctx c0 = global_ctx(I, B, 0, red);
             const int64_t g = greedy<TE>(c0, tc, J.seed, I.svc_sum, tid, nthr);
-            if (tid == 0) xs->init_obj = g;
+            if (tid == 0) __hip_atomic_store(&B.init_obj, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             snapshot(c0, J, tid, nthr);
         }
         for (int k = gtid; k < M * V; k += gthr) tabu[k] = (TB)0;
-        if (!grid_barrier(xs, nwg, nb, flag)) aborted = true;
-        cur = xs->init_obj;
+        if (!job_barrier(B, nwg, nb, flag)) aborted = true;
+        cur = __hip_atomic_load(&B.init_obj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         best = cur;
         best_iter = -1;
         stopped = 0;
     }
+    if (!aborted) {
+        // records of the current routes
+        GMove none{};
+        const Ctx c = global_ctx(I, B, p, red);
+        prep_next<TE>(c, c, none, tc, false, gtid, gthr);
+        if (!job_barrier(B, nwg, nb, flag)) aborted = true;
+    }
 
     const bool use_tabu = J.variant == AT_TABU;
-    const int gw = wg * nwaves + wave, TW = nwaves * nwg;
     int t = J.t_begin;
     for (; !aborted && t < J.t_end && !stopped; ++t) {
-        const Ctx c = global_ctx(I, B, p, red, J.chunk);
-        prep<TE>(c, tc, gtid, gthr);
+        const Ctx c = global_ctx(I, B, p, red);
         if (pending && writer) snapshot(c, J, tid, nthr);
         pending = false;
-        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
         int thr = INT32_MIN;
         if (J.aspiration) {
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, tabu, smem, J.gk, J.gnr, wg, nwg,
+        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, tabu, smem, red + 128, J.gk, wg, nwg,
                                          t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
@@ -927,26 +1183,19 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? red[lane] : kKeyNone;
             w = wave_min(w);
-            if (lane == 0) __hip_atomic_fetch_min(&xs->key[t % 3], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) __hip_atomic_fetch_min(&B.key[t % 3], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
-        const uint64_t key = __hip_atomic_load(&xs->key[t % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!job_barrier(B, nwg, nb, flag)) { aborted = true; break; }
+        const uint64_t key = __hip_atomic_load(&B.key[t % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the slot the iteration after next will use; every workgroup has read it
         if (writer && tid == 0)
-            __hip_atomic_store(&xs->key[(t + 2) % 3], kKeyNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&B.key[(t + 2) % 3], kKeyNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (key == kKeyNone) {
             if (!use_tabu) { stopped = 1; break; }
+            // nothing to apply: routes and records stay as they are
             if (writer && tid == 0 && J.trace) {
                 J.tr_move[t] = 0xFFFFFFFFu; J.tr_delta[t] = 0; J.tr_obj[t] = cur; J.tr_flags[t] = 0;
             }
-            // routes unchanged: copy them to the other buffer
-            const Ctx n = global_ctx(I, B, p ^ 1, red, J.chunk);
-            for (int kk = gtid; kk < M; kk += gthr) {
-                n.seq[kk] = c.seq[kk]; n.rt[kk] = c.rt[kk];
-                n.pof[kk] = c.pof[kk]; n.rof[kk] = c.rof[kk];
-            }
-            for (int r = gtid; r <= V; r += gthr) n.off[r] = c.off[r];
-            if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
-            p ^= 1;
             continue;
         }
         const bool blocked = (key >> 63) != 0;
@@ -955,8 +1204,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
         if (!use_tabu && d >= 0) { stopped = 1; break; }
         const int tval = t + J.tenure + 1;
         const bool is_swap = idx >= c.R;
-        const Ctx n = global_ctx(I, B, p ^ 1, red, J.chunk);
-        bool was_tabu;
+        GMove mv{};
+        bool was_tabu = false;
         if (!is_swap) {
             const int m = (int)(idx / (uint32_t)c.NG);
             const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
@@ -966,35 +1215,13 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
             const int rs = c.rt[s];
             const int fp = c.off[v] + g;
             const int q = fp - (fp > s ? 1 : 0);
-            was_tabu = use_tabu && (int)tabu[v * M + m] > t;
-            const int lo = min(s, q), hi = max(s, q);
-            auto offn = [&](int r) {
-                int o = c.off[r];
-                if (v > rs && r > rs && r <= v) o -= 1;
-                if (v < rs && r > v && r <= rs) o += 1;
-                return o;
-            };
-            for (int kk = gtid; kk < M; kk += gthr) {
-                int mm, r;
-                if (kk >= lo && kk <= hi) {
-                    mm = (kk == q) ? m : (q >= s ? c.seq[kk + 1] : c.seq[kk - 1]);
-                    int a = 0, b = V - 1;
-                    while (a < b) {
-                        const int mid = (a + b + 1) >> 1;
-                        if (offn(mid) <= kk) a = mid; else b = mid - 1;
-                    }
-                    r = a;
-                } else {
-                    mm = c.seq[kk];
-                    r = c.rt[kk];
-                }
-                n.seq[kk] = (uint16_t)mm;
-                n.rt[kk] = (uint16_t)r;
-                n.pof[mm] = (uint16_t)kk;
-                n.rof[mm] = (uint16_t)r;
+            mv.kind = 1;
+            mv.m = m; mv.v = v; mv.q = q; mv.rs = rs;
+            mv.lo = min(s, q); mv.hi = max(s, q); mv.dir = q >= s ? 1 : -1;
+            if (writer && tid == 0 && use_tabu) {
+                was_tabu = (int)tabu[v * M + m] > t;
+                tabu[rs * M + m] = (TB)tval;
             }
-            for (int r = gtid; r <= V; r += gthr) n.off[r] = offn(r);
-            if (writer && tid == 0 && use_tabu) tabu[rs * M + m] = (TB)tval;
         } else {
             const uint32_t sp = idx - c.R;
             const double A = 2.0 * (double)M - 1.0;
@@ -1005,22 +1232,16 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
             while (a > 0 && rowstart(a) > (int64_t)sp) --a;
             const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
             const int s1 = c.pof[m1], s2 = c.pof[m2];
-            const int r1 = c.rt[s1], r2 = c.rt[s2];
-            was_tabu = use_tabu && ((int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t);
-            for (int kk = gtid; kk < M; kk += gthr) {
-                const int mm = kk == s1 ? m2 : (kk == s2 ? m1 : (int)c.seq[kk]);
-                const int r = c.rt[kk];
-                n.seq[kk] = (uint16_t)mm;
-                n.rt[kk] = (uint16_t)r;
-                n.pof[mm] = (uint16_t)kk;
-                n.rof[mm] = (uint16_t)r;
-            }
-            for (int r = gtid; r <= V; r += gthr) n.off[r] = c.off[r];
+            mv.kind = 2;
+            mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
             if (writer && tid == 0 && use_tabu) {
+                const int r1 = c.rt[s1], r2 = c.rt[s2];
+                was_tabu = (int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t;
                 tabu[r1 * M + m1] = (TB)tval;
                 tabu[r2 * M + m2] = (TB)tval;
             }
         }
+        prep_next<TE>(c, global_ctx(I, B, p ^ 1, red), mv, tc, true, gtid, gthr);
         cur += d;
         if (writer && tid == 0 && J.trace) {
             J.tr_move[t] = idx;
@@ -1033,11 +1254,11 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
             best_iter = t;
             pending = true;
         }
-        if (!grid_barrier(xs, nwg, nb, flag)) { aborted = true; break; }
+        if (!job_barrier(B, nwg, nb, flag)) { aborted = true; break; }
         p ^= 1;
     }
     if (!writer) return;
-    if (pending && !aborted) snapshot(global_ctx(I, B, p, red, J.chunk), J, tid, nthr);
+    if (pending && !aborted) snapshot(global_ctx(I, B, p, red), J, tid, nthr);
     if (tid == 0) {
         J.scal->best_obj = best;
         J.scal->final_obj = cur;
@@ -1057,15 +1278,37 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, Xchg *xs, char 
     }
 }
 
+// Solves on the global schedule, each on its range [g0, g0 + ng) of the grid.
+// At most kGlobalBlock threads per workgroup: the register budget that leaves
+// (256 VGPRs) keeps the per-iteration state out of scratch memory.
 template <typename TE, typename TB>
-__global__ void __launch_bounds__(1024) k_search_global(const JobDev *job, Xchg *xs)
+__global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jobs, int n_jobs)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const JobDev &J = *job;
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].g0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const JobDev &J = jobs[lo];
     const InstDev &I = *J.inst;
-    const uint32_t lds = global_lds_bytes(J.gk, J.gnr, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
-    uint64_t *red = (uint64_t *)(smem + lds - 1024);
-    run_job_global<TE, TB>(J, (int)blockIdx.x, (int)gridDim.x, xs, smem, red);
+    const uint32_t lds = global_lds_bytes(J.gk, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
+    uint64_t *red = (uint64_t *)(smem + lds - 2048);
+    run_job_global<TE, TB>(J, b - J.g0, J.ng, smem, red);
+}
+
+// Clear the exchange state of every solve of a global-schedule launch.
+__global__ void k_reset_global(const JobDev *jobs, int n_jobs)
+{
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n_jobs; i += (int)(gridDim.x * blockDim.x)) {
+        GlobalBufs &B = *jobs[i].gb;
+        B.key[0] = kKeyNone;
+        B.key[1] = kKeyNone;
+        B.key[2] = kKeyNone;
+        B.cnt = 0;
+        B.abort = 0;
+    }
 }
 
 // One workgroup per job; jobs are taken from an atomic queue until exhausted.
@@ -1191,23 +1434,26 @@ hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int bl
 }
 
 template <typename TE, typename TB>
-static hipError_t coop_launch_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+static hipError_t coop_launch_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                      uint32_t lds_bytes, hipStream_t s)
 {
     hipError_t e = set_lds(k_search_global<TE, TB>, lds_bytes);
     if (e != hipSuccess) return e;
-    void *args[] = {(void *)&job, (void *)&xs};
+    void *args[] = {(void *)&jobs, (void *)&n_jobs};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search_global<TE, TB>),
                                       dim3(n_groups), dim3(block), args, lds_bytes, s);
 }
 
-hipError_t launch_search_global(const JobDev *job, Xchg *xs, int n_groups, int block,
+hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s)
 {
-    if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
-    if (esz16) return coop_launch_global<uint16_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
-    if (tb16) return coop_launch_global<int32_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
-    return coop_launch_global<int32_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
+    k_reset_global<<<dim3((unsigned)((n_jobs + 255) / 256)), dim3(256), 0, s>>>(jobs, n_jobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(jobs, n_jobs, n_groups, block, lds_bytes, s);
+    if (esz16) return coop_launch_global<uint16_t, int32_t>(jobs, n_jobs, n_groups, block, lds_bytes, s);
+    if (tb16) return coop_launch_global<int32_t, uint16_t>(jobs, n_jobs, n_groups, block, lds_bytes, s);
+    return coop_launch_global<int32_t, int32_t>(jobs, n_jobs, n_groups, block, lds_bytes, s);
 }
 
 template <typename TE, typename TB>

@@ -210,6 +210,8 @@ struct Server {
             ih.push_back(active[k]->host_inst);
         }
         const std::vector<int> order = order_jobs(jobs);
+        int rc0 = assign_groups(jobs, order);
+        if (rc0) return rc0;
         std::vector<JobDev> hj(jobs.size());
         for (size_t k = 0; k < order.size(); ++k) {
             Request *r = active[(size_t)order[k]];

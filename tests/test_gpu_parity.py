@@ -227,6 +227,19 @@ def test_global_schedule_edge_cases():
         assert_same_result(o, g, f"global {V}x{M}")
 
 
+@pytest.mark.parametrize("groups", [1, 16, 64])
+def test_global_schedule_short_routes(groups):
+    """24 vehicles x 40 missions: a block of consecutive positions spans more
+    routes than the eval stages tabu rows for (the rest read from HBM), and the
+    group count sets the block size (8, 2 and 1 missions)."""
+    inst = make_instance(77, 60, 6, 24, 40)
+    for variant in (at.AT_TABU, at.AT_NS):
+        _, o = oracle_solve(inst, variant=variant, tenure=5, iters=120)
+        g = at.solve(_dev(inst), variant=variant, tenure=5, iters=120, schedule=at.SCHED_GLOBAL,
+                     n_groups=groups)
+        assert_same_result(o, g, f"global 24x40 variant {variant} groups {groups}")
+
+
 def test_stress_instance_prefix():
     """The 256-vehicle x 10000-mission instance: greedy start and the first
     iterations against the oracle (each oracle iteration scores 1.5e8 moves)."""
