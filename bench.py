@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serve", type=str, default="",
                     help="also run the serving stream at these arrival rates (req/s, comma separated)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-chunk", type=int, default=50, help="iterations per serving launch")
+    ap.add_argument("--serve-slots", type=int, default=256, help="concurrent solves in the server")
     ap.add_argument("--stress", type=int, default=0,
                     help="also run the 256 x 10000 stress instance for this many iterations (Tabu and NS)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -201,7 +203,11 @@ def main():
     if args.stress:
         line["stress"] = bench_stress(args.stress)
     if args.serve:
-        line["serving"] = [bench_serve(float(x), args.serve_requests) for x in args.serve.split(",")]
+        rates = [float(x) for x in args.serve.split(",")]
+        line["serving"] = [bench_serve(lam, args.serve_requests, chunk=args.serve_chunk,
+                                       slots=args.serve_slots,
+                                       plain_sample=32 if k == len(rates) - 1 else 0)
+                           for k, lam in enumerate(rates)]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(line))
@@ -294,7 +300,7 @@ def bench_stress(iters: int):
 
 
 def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,
-                budget: int = 64 << 30):
+                budget: int = 64 << 30, plain_sample: int = 0):
     """Open-loop Poisson stream of n_req requests at rate lam through the
     continuous-batching server; latency = result on the host minus scheduled
     arrival.  Instances are uploaded before the clock starts."""
@@ -334,10 +340,28 @@ def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,
     wall = time.perf_counter() - t0
     srv.close()
     lat = np.array([done[k] - arrivals[k] for k in range(n_req)]) * 1000.0
-    return {"lambda_req_per_s": lam, "requests": n_req, "wall_s": wall,
-            "solves_per_s": n_req / wall, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
-            "chunk_iters": chunk, "max_slots": slots}
+    out = {"lambda_req_per_s": lam, "requests": n_req, "wall_s": wall,
+           "solves_per_s": n_req / wall, "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+           "chunk_iters": chunk, "max_slots": slots}
+    if plain_sample:
+        # the plain per-instance form: one at_solve per request, in arrival order, on
+        # a sample of the stream; its move-eval rate applied to the stream's mix
+        work = [sum(move_counts(s["n_missions"], s["n_vehicles"])) * s["iters"] for s in specs]
+        n_p = min(plain_sample, n_req)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(n_p):
+            s = specs[k]
+            r = at.solve(devs[k], variant=at.AT_TABU, tenure=s["tenure"], iters=s["iters"], trace=False)
+            assert r["status"] == 0
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t1
+        plain_sps = (sum(work[:n_p]) / t_plain) / (sum(work) / n_req)
+        out.update({"plain_sample_solves": n_p, "plain_sample_s": t_plain,
+                    "plain_solves_per_s": plain_sps,
+                    "speedup_vs_plain": (n_req / wall) / plain_sps})
+    return out
 
 
 if __name__ == "__main__":

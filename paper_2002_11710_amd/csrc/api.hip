@@ -94,7 +94,7 @@ size_t inst_bytes(const at_instance &in, bool with_t)
     o += al256(4 * (size_t)in.n_locs) * 2;
     o += al256(4 * (size_t)in.n_missions) * 2;
     o += al256(4 * (size_t)in.n_vehicles) * 2;
-    o += al256((size_t)tc_capacity(in.n_locs, in.n_missions, in.n_vehicles)) * (with_t ? 2 : 1);
+    o += al256((size_t)tc_capacity(in.n_locs, in.n_missions, in.n_vehicles)) * (with_t ? 3 : 1);
     return o;
 }
 
@@ -118,6 +118,7 @@ void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
     d.tc_cap = tc_capacity(in.n_locs, in.n_missions, in.n_vehicles);
     o += al256((size_t)d.tc_cap);
     d.tct = with_t ? (void *)(base + o) : nullptr;
+    d.tcr = with_t ? (void *)(base + o + al256((size_t)d.tc_cap)) : nullptr;
     d.status = AT_EDEVICE;
 }
 
@@ -186,18 +187,38 @@ static WsPlan plan_ws(int32_t n_inst, const at_instance *insts, const at_params 
 // ---------------------------------------------------------------------------
 // prepare: upload descriptors, run the checks, read back per-instance results
 // ---------------------------------------------------------------------------
-int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s)
+// Enqueue the prepare launches of n_inst instances (device table `dev`, host
+// copies `host`, which must stay valid until the stream has passed the
+// read-back enqueued here).
+int prepare_enqueue(int32_t n_inst, InstDev *dev, InstDev *host, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(dev, host.data(), sizeof(InstDev) * (size_t)n_inst,
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "upload instances");
-    if ((e = launch_prepare(dev, n_inst, s)) != hipSuccess) return hip_fail(e, "prepare launch");
-    if ((e = hipMemcpyAsync(host.data(), dev, sizeof(InstDev) * (size_t)n_inst,
-                            hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return hip_fail(e, "read back instances");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "prepare");
+    int64_t sc = 0, fc = 0;
     for (int32_t i = 0; i < n_inst; ++i) {
-        const InstDev &d = host[(size_t)i];
+        InstDev &h = host[i];
+        int64_t f = 0;
+        const int64_t c = prepare_chunks(h, &f);
+        h.scan0 = (int32_t)sc;
+        h.fill0 = (int32_t)fc;
+        sc += c;
+        fc += f;
+        h.maxT = 0;
+        h.scan_bad = 0;
+        h.status = AT_EDEVICE;
+        if (sc > INT32_MAX || fc > INT32_MAX) return fail(AT_ENOMEM, "too many travel entries in one call");
+    }
+    hipError_t e = hipMemcpyAsync(dev, host, sizeof(InstDev) * (size_t)n_inst, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "upload instances");
+    if ((e = launch_prepare(dev, n_inst, sc, fc, s)) != hipSuccess) return hip_fail(e, "prepare launch");
+    if ((e = hipMemcpyAsync(host, dev, sizeof(InstDev) * (size_t)n_inst, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "read back instances");
+    return AT_OK;
+}
+
+// Status of prepared instances (after the stream has passed prepare_enqueue's read-back).
+int prepare_check(int32_t n_inst, const InstDev *host)
+{
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const InstDev &d = host[i];
         if (d.status == AT_EINVAL)
             return fail(AT_EINVAL, "instance %d: mission or vehicle location out of range, or pickup == delivery", i);
         if (d.status == AT_ERANGE)
@@ -205,6 +226,15 @@ int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, 
         if (d.status != AT_OK) return fail(AT_EDEVICE, "instance %d: prepare status %d", i, d.status);
     }
     return AT_OK;
+}
+
+int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s)
+{
+    int rc = prepare_enqueue(n_inst, dev, host.data(), s);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "prepare");
+    return prepare_check(n_inst, host.data());
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +258,18 @@ static int pick_chunk(const at_params &pr, int64_t slots)
     return 32;
 }
 
+// Missions per block of a global-schedule job for its group count: one block
+// per workgroup where LDS allows, else the LDS limit.
+static void set_block_size(JobHost &h)
+{
+    // as few rounds of blocks as LDS allows, then the smallest blocks with that many rounds
+    const int64_t g = std::max(1, h.groups);
+    const int64_t rounds = std::max<int64_t>(1, (h.dM + g * h.gkmax - 1) / (g * h.gkmax));
+    const int per = (int)((h.dM + rounds * g - 1) / (rounds * g));
+    h.gk = std::max(1, std::min(h.gkmax, per));
+    h.lds = global_lds_bytes(h.gk, h.dR, h.dC, h.dM, h.dV, h.desz, h.tb16 ? 2 : 4);
+}
+
 int plan_job(JobHost &h, const InstDev &d, bool alone)
 {
     h.slots = n_slots(d.M, d.V);
@@ -245,17 +287,18 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
         if (!d.tct) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but its transposed block was not reserved");
         const int g = h.pr.n_groups ? h.pr.n_groups
                                     : (int)std::max<int64_t>(1, std::min<int64_t>(num_cus(), h.slots / 16384));
-        // the most missions per block that LDS holds while every workgroup still gets a block
-        h.gk = 0;
-        for (int K = kGlobalKMax; K >= 1; K >>= 1) {
-            if (K > 1 && (d.M + K - 1) / K < g) continue;
-            const uint32_t b = global_lds_bytes(K, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4);
-            if (b <= kLdsLimit) { h.gk = K; h.lds = b; break; }
-        }
-        if (!h.gk) return fail(AT_ENOMEM, "instance too large: %d exit and %d entry locations do not fit the staged search", d.R, d.C);
+        h.dM = d.M; h.dV = d.V; h.dR = d.R; h.dC = d.C; h.desz = d.esz;
+        // the most missions per block that LDS holds (the block size itself is set
+        // with the final group count: one block per workgroup where LDS allows)
+        h.gkmax = 0;
+        for (int K = kGlobalKMax; K >= 1; --K)
+            if (global_lds_bytes(K, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4) <= kLdsLimit) { h.gkmax = K; break; }
+        if (!h.gkmax) return fail(AT_ENOMEM, "instance too large: %d exit and %d entry locations do not fit the staged search", d.R, d.C);
+        h.lds = global_lds_bytes(h.gkmax, d.R, d.C, d.M, d.V, d.esz, h.tb16 ? 2 : 4);
         const int cap = max_groups_global(h.block, h.lds, h.tb16, h.esz16);
         if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
         h.groups = std::max(1, std::min(g, cap));
+        set_block_size(h);
         return AT_OK;
     }
     h.kind = AT_SCHED_WG;
@@ -312,16 +355,19 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
 // Upload GlobalBufs pointer tables for the jobs on the global schedule.
 int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s)
 {
+    // the host copies are the copy sources: they live until the synchronisation below
+    std::vector<GlobalBufs> host;
+    host.reserve(jobs.size());
     for (const auto &h : jobs) {
         if (h.kind != AT_SCHED_GLOBAL) continue;
-        GlobalBufs g;
-        carve_gstate(g, ih[(size_t)h.inst].M, ih[(size_t)h.inst].V, h.tb16 ? 2 : 4, (char *)h.gstate);
-        hipError_t e = hipMemcpyAsync(h.gstate, &g, sizeof(g), hipMemcpyHostToDevice, s);
+        host.emplace_back();
+        carve_gstate(host.back(), ih[(size_t)h.inst].M, ih[(size_t)h.inst].V, h.tb16 ? 2 : 4, (char *)h.gstate);
+        hipError_t e = hipMemcpyAsync(h.gstate, &host.back(), sizeof(GlobalBufs), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "upload state tables");
-        // a synchronous copy source must stay alive until the copy is done
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "upload state tables");
     }
-    return AT_OK;
+    if (host.empty()) return AT_OK;
+    hipError_t e = hipStreamSynchronize(s);
+    return e == hipSuccess ? AT_OK : hip_fail(e, "upload state tables");
 }
 
 // Internal streams on which the one-workgroup-per-job launches of different
@@ -490,6 +536,7 @@ int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
                 h.g0 = g0;
                 h.launch = launch;
                 g0 += h.groups;
+                set_block_size(h);
             }
         }
         k = e;

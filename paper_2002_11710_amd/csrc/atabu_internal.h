@@ -62,11 +62,15 @@ struct InstDev {
     int32_t *mrow, *mcol, *vrow, *vcol;
     void *tc;                         // workspace, capacity tc_cap bytes
     void *tct;                        // transposed block (C rows, stride Rs) or null
+    void *tcr;                        // the block again with 16-byte aligned rows (stride Cg), or null
     int64_t tc_cap;
-    // filled by the prepare kernel
+    int32_t scan0, fill0;             // first chunk of this instance in the scan / fill launches
+    int32_t scan_bad;                 // a travel time outside [0, 2^23) (scan launch)
+    // filled by the prepare kernels
     int32_t status;
     int32_t R, C, Cs, esz;            // esz = 2 or 4 bytes per compact entry
     int32_t Rs;                       // row stride of the transposed block
+    int32_t Cg;                       // row stride of the aligned copy
     int32_t maxT;
     int64_t svc_sum;
 };
@@ -204,7 +208,9 @@ __host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_travel(int32_t n, const double *lat, const double *lon, double speed,
                          int32_t *out, hipStream_t s);
-hipError_t launch_prepare(InstDev *insts, int32_t n, hipStream_t s);
+// chunks of the travel scan of one instance (returned) and of its block fill (out)
+int64_t prepare_chunks(const InstDev &h, int64_t *fill_chunks);
+hipError_t launch_prepare(InstDev *insts, int32_t n, int64_t scan_chunks, int64_t fill_chunks, hipStream_t s);
 hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid, int block,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
@@ -213,27 +219,35 @@ hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, in
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
 // Missions staged per block by the global schedule's eval, at most.
-constexpr int kGlobalKMax = 8;
+constexpr int kGlobalKMax = 64;
 // Threads per workgroup of the global schedule, at most.
 constexpr int kGlobalBlock = 512;
 
 // Staged lengths (elements) of the travel vectors of the global schedule's
-// eval: a column of the block (R exit rows) in whole 16-byte chunks, a row
-// (C entry columns) in whole 8-byte pieces.  The transposed block's row stride
-// is the column length, so its rows are 16-byte aligned.
+// eval: a column of the block (R exit rows) and a row (C entry columns), each
+// in whole 16-byte chunks.  They are also the row strides of the transposed
+// block and of the aligned copy, whose rows are therefore 16-byte aligned.
 __host__ __device__ inline int staged_rows(int R, int esz) { const int q = 16 / esz; return (R + q - 1) / q * q; }
-__host__ __device__ inline int staged_cols(int C, int esz) { const int q = 8 / esz; return (C + q - 1) / q * q; }
+__host__ __device__ inline int staged_cols(int C, int esz) { const int q = 16 / esz; return (C + q - 1) / q * q; }
 
-// LDS bytes of the global schedule's mission-major eval: K missions' four
-// travel vectors and tabu columns, one tabu bit row (M bits) per vehicle of the
-// block (at most K), then 2 KiB of reduction slots and per-block tables.
+// Per-block tables of the global schedule's eval: 4 source pointers, two int4
+// records and a vehicle slot per mission, and the vehicle count.
+__host__ __device__ inline uint32_t global_table_bytes(int K)
+{
+    return (uint32_t)(32 * K + 32 * K + ((4 * K + 4 + 15) & ~15));
+}
+
+// LDS bytes of the global schedule's mission-major eval: the per-block tables,
+// K missions' four travel vectors and tabu columns, one tabu bit row (M bits)
+// per vehicle of the block (at most K), then 2 KiB of reduction slots.
 __host__ __device__ inline uint32_t global_lds_bytes(int K, int R, int C, int M, int V, int esz, int tbsz)
 {
     const uint64_t Re = (uint64_t)staged_rows(R, esz), Ce = (uint64_t)staged_cols(C, esz);
     const uint64_t vec = (uint64_t)K * (2 * Re + 2 * Ce) * (uint64_t)esz;
     const uint64_t tk = (uint64_t)K * (uint64_t)V * (uint64_t)tbsz;
     const uint64_t rb = (uint64_t)K * (((uint64_t)M + 31) / 32) * 4;
-    const uint64_t tot = ((vec + 15) & ~15ull) + ((tk + 15) & ~15ull) + ((rb + 15) & ~15ull) + 2048;
+    const uint64_t tot = global_table_bytes(K) + ((vec + 15) & ~15ull) + ((tk + 15) & ~15ull)
+                       + ((rb + 15) & ~15ull) + 2048;
     return tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
 }
 hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_t *seq,

@@ -27,7 +27,8 @@ struct JobHost {
     uint32_t lds = 0;
     int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
-    int gk = 0;                       // global schedule: missions staged per block
+    int gk = 0, gkmax = 0;            // global schedule: missions staged per block (chosen, LDS limit)
+    int dM = 0, dV = 0, dR = 0, dC = 0, desz = 4;   // instance sizes (global schedule LDS plan)
     int g0 = 0, launch = 0;           // global schedule: first workgroup, launch index (assign_groups)
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
 };
@@ -42,6 +43,8 @@ size_t inst_bytes(const at_instance &in, bool with_t);
 size_t gstate_bytes(const at_instance &in, const at_params &pr);
 void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t);
 void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base);
+int prepare_enqueue(int32_t n_inst, InstDev *dev, InstDev *host, hipStream_t s);
+int prepare_check(int32_t n_inst, const InstDev *host);
 int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s);
 int plan_job(JobHost &h, const InstDev &d, bool alone);
 int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal);

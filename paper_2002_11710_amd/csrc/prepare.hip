@@ -1,21 +1,30 @@
 // prepare.hip -- per-instance checks and the compact exit x entry travel block.
 //
-// One workgroup per instance:
-//   1. check every mission (pickup, delivery inside [0, L), pickup != delivery)
-//      and vehicle base, and every travel time inside [0, 2^23);
-//   2. mark the exit locations (deliveries, bases) and entry locations
-//      (pickups, bases) in LDS bitmaps and rank them by a prefix sum of
-//      popcounts, so both are numbered in increasing location order;
-//   3. copy the R x C block T[exit_loc[r]][enter_loc[c]] into the workspace with
-//      row stride Cs, as uint16 when every travel time is below 2^16;
-//   4. store each mission's (delivery row * Cs, pickup column) and each
-//      vehicle's (base row * Cs, base column), and the sum of the loaded legs.
+// Three launches, each covering every instance of the call:
+//   k_scan_travel  (many workgroups per instance, 4096 entries each): every
+//                  travel time inside [0, 2^23), and the largest one;
+//   k_prepare      (one workgroup per instance): check every mission (pickup,
+//                  delivery inside [0, L), pickup != delivery) and vehicle base;
+//                  mark the exit locations (deliveries, bases) and entry
+//                  locations (pickups, bases) in LDS bitmaps and rank them by a
+//                  prefix sum of popcounts, so both are numbered in increasing
+//                  location order; store each mission's (delivery row * Cs,
+//                  pickup column), each vehicle's (base row * Cs, base column),
+//                  the entry width, the strides and the sum of the loaded legs;
+//   k_fill_blocks  (many workgroups per instance): copy the R x C block
+//                  T[exit_loc[r]][enter_loc[c]] with row stride Cs, as uint16
+//                  when every travel time is below 2^16, and, for solves that
+//                  may take the HBM-resident schedule, the same block
+//                  transposed (stride Rs) and with 16-byte aligned rows (stride Cg).
+// A workgroup of the two many-workgroup kernels finds its instance from the
+// per-instance first-chunk indices scan0 / fill0 the host fills in.
 #include "atabu_internal.h"
 #include "atabu.h"
 
 namespace at {
 
 constexpr int kPrepThreads = 256;
+constexpr int kChunk = 4096;                       // entries per workgroup of scan and fill
 constexpr int kMaxWords = (kMaxLocs + 31) / 32;   // 2048
 
 __device__ __forceinline__ int rank_of(const uint32_t *bm, const uint32_t *pf, int loc)
@@ -25,11 +34,41 @@ __device__ __forceinline__ int rank_of(const uint32_t *bm, const uint32_t *pf, i
     return (int)pf[w] + __popc(below);
 }
 
+// instance whose chunk range [first(i), first(i + 1)) holds chunk b
+template <typename F>
+__device__ __forceinline__ int owner(int n, int64_t b, F first)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kPrepThreads) k_scan_travel(InstDev *insts, int n)
+{
+    const int64_t b = blockIdx.x;
+    const int i = owner(n, b, [&](int k) { return (int64_t)insts[k].scan0; });
+    InstDev &I = insts[i];
+    const int64_t nn = (int64_t)I.L * I.L;
+    const int64_t k0 = (b - I.scan0) * kChunk;
+    int lmax = 0, bad = 0;
+    for (int64_t k = k0 + threadIdx.x; k < min(nn, k0 + kChunk); k += blockDim.x) {
+        const int x = I.T[k];
+        bad |= (x < 0 || x >= kMaxTravel) ? 1 : 0;
+        lmax = x > lmax ? x : lmax;
+    }
+    if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(&I.scan_bad, 1);
+    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&I.maxT, lmax);
+}
+
 __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
 {
     __shared__ uint32_t bmx[kMaxWords], bme[kMaxWords], pfx[kMaxWords], pfe[kMaxWords];
     __shared__ uint32_t part_x[kPrepThreads], part_e[kPrepThreads];
-    __shared__ int s_bad, s_max;
+    __shared__ int s_bad;
     __shared__ unsigned long long s_svc;
 
     InstDev &I = insts[blockIdx.x];
@@ -39,7 +78,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     const int32_t *__restrict__ T = I.T;
 
     for (int w = tid; w < nw; w += nthr) { bmx[w] = 0; bme[w] = 0; }
-    if (tid == 0) { s_bad = 0; s_max = 0; s_svc = 0; }
+    if (tid == 0) { s_bad = 0; s_svc = 0; }
     __syncthreads();
 
     int64_t svc = 0;
@@ -55,17 +94,9 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
         atomicOr(&bme[b >> 5], 1u << (b & 31));
         atomicOr(&bmx[b >> 5], 1u << (b & 31));
     }
-    int lmax = 0;
-    const int64_t nn = (int64_t)L * L;
-    for (int64_t k = tid; k < nn; k += nthr) {
-        const int x = T[k];
-        if (x < 0 || x >= kMaxTravel) { atomicOr(&s_bad, 2); break; }
-        lmax = x > lmax ? x : lmax;
-    }
-    atomicMax(&s_max, lmax);
     __syncthreads();
-    if (s_bad) {
-        if (tid == 0) I.status = (s_bad & 1) ? AT_EINVAL : AT_ERANGE;
+    if (s_bad || I.scan_bad) {
+        if (tid == 0) I.status = s_bad ? AT_EINVAL : AT_ERANGE;
         return;
     }
     for (int m = tid; m < M; m += nthr) svc += T[(int64_t)I.p[m] * L + I.d[m]];
@@ -99,10 +130,12 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     __syncthreads();
 
     const int R = I.R, C = I.C;
-    const int esz = s_max <= 65535 ? 2 : 4;
+    const int esz = I.maxT <= 65535 ? 2 : 4;
     const int Cs = compact_stride(C, esz);
     const int Rs = staged_rows(R, esz);
-    if ((int64_t)R * Cs * esz > I.tc_cap || (I.tct && (int64_t)C * Rs * esz > I.tc_cap)) {
+    const int Cg = staged_cols(C, esz);
+    if ((int64_t)R * Cs * esz > I.tc_cap ||
+        (I.tct && ((int64_t)C * Rs * esz > I.tc_cap || (int64_t)R * Cg * esz > I.tc_cap))) {
         if (tid == 0) I.status = AT_ENOMEM;
         return;
     }
@@ -114,38 +147,6 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
         bits = bme[w];
         r = (int)pfe[w];
         while (bits) { const int b = __ffs(bits) - 1; I.enter_loc[r++] = w * 32 + b; bits &= bits - 1u; }
-    }
-    __syncthreads();
-    const int64_t total = (int64_t)R * Cs;
-    if (esz == 2) {
-        uint16_t *tc = (uint16_t *)I.tc;
-        for (int64_t k = tid; k < total; k += nthr) {
-            const int r = (int)(k / Cs), c = (int)(k - (int64_t)r * Cs);
-            tc[k] = c < C ? (uint16_t)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (uint16_t)0;
-        }
-    } else {
-        int32_t *tc = (int32_t *)I.tc;
-        for (int64_t k = tid; k < total; k += nthr) {
-            const int r = (int)(k / Cs), c = (int)(k - (int64_t)r * Cs);
-            tc[k] = c < C ? T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : 0;
-        }
-    }
-    if (I.tct) {
-        // the same block transposed (entry-major), for the HBM-resident schedule
-        const int64_t tt = (int64_t)C * Rs;
-        if (esz == 2) {
-            uint16_t *tct = (uint16_t *)I.tct;
-            for (int64_t k = tid; k < tt; k += nthr) {
-                const int c = (int)(k / Rs), r = (int)(k - (int64_t)c * Rs);
-                tct[k] = r < R ? (uint16_t)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (uint16_t)0;
-            }
-        } else {
-            int32_t *tct = (int32_t *)I.tct;
-            for (int64_t k = tid; k < tt; k += nthr) {
-                const int c = (int)(k / Rs), r = (int)(k - (int64_t)c * Rs);
-                tct[k] = r < R ? T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : 0;
-            }
-        }
     }
     for (int m = tid; m < M; m += nthr) {
         I.mrow[m] = rank_of(bmx, pfx, I.d[m]) * Cs;
@@ -159,17 +160,64 @@ __global__ void __launch_bounds__(kPrepThreads) k_prepare(InstDev *insts)
     if (tid == 0) {
         I.Cs = Cs;
         I.Rs = Rs;
+        I.Cg = Cg;
         I.esz = esz;
-        I.maxT = s_max;
         I.svc_sum = (int64_t)s_svc;
         I.status = AT_OK;
     }
 }
 
-hipError_t launch_prepare(InstDev *insts, int32_t n, hipStream_t s)
+template <typename TE>
+__device__ __forceinline__ void fill_chunk(const InstDev &I, int64_t k0)
+{
+    const int L = I.L, R = I.R, C = I.C, Cs = I.Cs, Rs = I.Rs, Cg = I.Cg;
+    const int32_t *__restrict__ T = I.T;
+    const int64_t n1 = (int64_t)R * Cs, n2 = I.tct ? (int64_t)C * Rs : 0, n3 = I.tcr ? (int64_t)R * Cg : 0;
+    TE *tc = (TE *)I.tc, *tct = (TE *)I.tct, *tcr = (TE *)I.tcr;
+    for (int64_t k = k0 + threadIdx.x; k < k0 + kChunk; k += blockDim.x) {
+        if (k < n1) {
+            const int r = (int)(k / Cs), c = (int)(k - (int64_t)r * Cs);
+            tc[k] = c < C ? (TE)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (TE)0;
+        }
+        if (k < n2) {
+            // the same block transposed (entry-major)
+            const int c = (int)(k / Rs), r = (int)(k - (int64_t)c * Rs);
+            tct[k] = r < R ? (TE)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (TE)0;
+        }
+        if (k < n3) {
+            // and row-major with 16-byte aligned rows
+            const int r = (int)(k / Cg), c = (int)(k - (int64_t)r * Cg);
+            tcr[k] = c < C ? (TE)T[(int64_t)I.exit_loc[r] * L + I.enter_loc[c]] : (TE)0;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kPrepThreads) k_fill_blocks(InstDev *insts, int n)
+{
+    const int64_t b = blockIdx.x;
+    const int i = owner(n, b, [&](int k) { return (int64_t)insts[k].fill0; });
+    const InstDev &I = insts[i];
+    if (I.status != AT_OK) return;
+    const int64_t k0 = (b - I.fill0) * kChunk;
+    if (I.esz == 2) fill_chunk<uint16_t>(I, k0);
+    else fill_chunk<int32_t>(I, k0);
+}
+
+int64_t prepare_chunks(const InstDev &h, int64_t *fill_chunks)
+{
+    const int64_t B = compact_bound(h.L, h.M, h.V);
+    if (fill_chunks) *fill_chunks = (B * (B + 8) + kChunk - 1) / kChunk;
+    return ((int64_t)h.L * h.L + kChunk - 1) / kChunk;
+}
+
+hipError_t launch_prepare(InstDev *insts, int32_t n, int64_t scan_chunks, int64_t fill_chunks, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
+    if (scan_chunks > 0)
+        hipLaunchKernelGGL(k_scan_travel, dim3((unsigned)scan_chunks), dim3(kPrepThreads), 0, s, insts, (int)n);
     hipLaunchKernelGGL(k_prepare, dim3((unsigned)n), dim3(kPrepThreads), 0, s, insts);
+    if (fill_chunks > 0)
+        hipLaunchKernelGGL(k_fill_blocks, dim3((unsigned)fill_chunks), dim3(kPrepThreads), 0, s, insts, (int)n);
     return hipGetLastError();
 }
 

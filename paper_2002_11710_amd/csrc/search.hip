@@ -865,77 +865,86 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
 }
 
 // Eval of the global schedule: blocks of K (at most kGlobalKMax) consecutive
-// route positions, dealt round-robin to the solve's workgroups.  For each
-// block the four travel vectors its missions' moves read -- the block column
-// of the pickup and of the successor (from the transposed block), the block
-// row of the delivery and of the predecessor -- the missions' tabu columns and
-// the tabu rows of the block's vehicles (one bit per mission: active or not)
-// are staged in LDS, each thread's loads issued before its first store.  Every
-// thread then streams gap records (relocates) and later positions (swaps) from
-// HBM/L2, UR or US in flight, and scores each against the K missions; inside
-// one (mission, round) the keys are 32-bit -- blocked bit, delta + 2^25, then
-// the column's rank -- and their minimum joins the 64-bit key of the lane.
-// Rounds that hold a no-op column, the mission's own neighbours or the tail
-// take a checked path; all others skip the checks.  `tab` is a 1 KiB LDS table:
-// 32 source pointers, then two int4 per mission, then the block's vehicles.
+// route positions, dealt round-robin to the solve's workgroups (one block per
+// workgroup where LDS allows).  For each block the four travel vectors its
+// missions' moves read -- the block column of the pickup and of the successor
+// (rows of the transposed block), the block row of the delivery and of the
+// predecessor (rows of the aligned copy) -- the missions' tabu columns and the
+// tabu rows of the block's vehicles (one bit per mission: active or not) are
+// staged in LDS with 16-byte loads, each thread's loads issued before its
+// first store.  The sweeps map threads two-dimensionally: Q threads (a power
+// of two, at least a wavefront) walk the columns -- gap records for
+// relocates, later positions for swaps, several in flight -- and nthr / Q
+// thread groups split the block's missions.  Inside one (mission, round) the
+// keys are 32-bit -- blocked bit, delta + 2^25, then the column's rank -- and
+// their minimum joins the 64-bit key of the lane.  Rounds that hold a no-op
+// column, the mission's own neighbours or the tail take a checked path; all
+// others skip the checks.
 template <typename TE, typename TB>
 __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
-                                const TB *tabu, char *smem, uint64_t *tab, int K, int wg, int nwg,
+                                const TE *tcr, const TB *tabu, char *smem, int K, int wg, int nwg,
                                 int t, int thr, bool use_tabu)
 {
     constexpr int UR = 8, US = 4, UL = 8;      // relocate, swap and staging loads in flight
     constexpr int ES = (int)sizeof(TE);
+    (void)tc;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
-    const int M = c.M, V = c.V, NG = c.NG, Rs = I.Rs;
+    const int M = c.M, V = c.V, NG = c.NG, Rs = I.Rs, Cg = I.Cg;
     const int Re = staged_rows(I.R, ES), Ce = staged_cols(I.C, ES);
-    const int R16 = Re * ES / 16;              // 16-byte chunks of a staged column
-    const int Cw = (I.C * ES + 3) / 4;         // 4-byte words of a staged row
+    const int R16 = Re * ES / 16, C16 = Ce * ES / 16;   // 16-byte chunks of a staged column / row
     const int per = 2 * Re + 2 * Ce;
     const int Wm = (M + 31) >> 5;
-    TE *vec = (TE *)smem;
-    TB *trow = (TB *)(smem + (((size_t)K * per * sizeof(TE) + 15) & ~(size_t)15));
+    uint64_t *tab = (uint64_t *)smem;             // source pointers, 4 per mission
+    int4 *mi = (int4 *)(tab + 4 * K);             // {m | r << 16, rem, own gap, out}
+    int4 *mi2 = mi + K;                           // {adjacent-swap delta, vehicle slot, -, -}
+    int *rl = (int *)(mi2 + K);                   // the block's vehicles; their count at rl[K]
+    TE *vec = (TE *)(smem + global_table_bytes(K));
+    TB *trow = (TB *)((char *)vec + (((size_t)K * per * sizeof(TE) + 15) & ~(size_t)15));
     uint32_t *rbits = (uint32_t *)((char *)trow + (((size_t)K * V * sizeof(TB) + 15) & ~(size_t)15));
-    int4 *mi = (int4 *)(tab + 4 * kGlobalKMax);   // {m | r << 16, rem, own gap, out}
-    int4 *mi2 = mi + kGlobalKMax;                 // {adjacent-swap delta, vehicle slot, -, -}
-    int *rl = (int *)(mi2 + kGlobalKMax);         // the block's vehicles; their count at rl[kGlobalKMax]
     const int th = use_tabu ? t : INT32_MAX;
     const int nblk = (M + K - 1) / K;
+    // relocate sweep shape: QR column threads, PR mission groups
+    int QR = kWave;
+    while (QR < nthr && QR * UR < NG) QR <<= 1;
+    const int PR = nthr / QR, pr = tid / QR, qr = tid - pr * QR;
     uint64_t best = kKeyNone;
     for (int blk = wg; blk < nblk; blk += nwg) {
         const int i0 = blk * K;
         const int kn = min(K, M - i0);
         __syncthreads();   // the previous block's LDS reads are done
-        if (tid < kn) {
-            const int4 pb = c.posB[i0 + tid];
-            const int r = (int)((uint32_t)pb.z >> 16);
-            mi[tid] = make_int4(pb.z, pb.y - pb.x, i0 + tid + r, pb.x);
-            mi2[tid] = make_int4((int)((uint32_t)pb.w >> 6) - kPackBias, 0, 0, 0);
-        } else if (tid >= kWave && tid < kWave + 4 * kn) {
-            const int q = tid - kWave, k = q >> 2, ty = q & 3;
-            const int4 pa = c.posA[i0 + k];
-            const TE *src = ty == 0 ? tct + (size_t)pa.y * Rs
-                          : ty == 1 ? tct + (size_t)pa.w * Rs
-                          : ty == 2 ? tc + pa.x : tc + pa.z;
-            tab[q] = (uint64_t)(uintptr_t)src;
+        for (int q = tid; q < 5 * kn; q += nthr) {
+            if (q < kn) {
+                const int4 pb = c.posB[i0 + q];
+                const int r = (int)((uint32_t)pb.z >> 16);
+                mi[q] = make_int4(pb.z, pb.y - pb.x, i0 + q + r, pb.x);
+                mi2[q] = make_int4((int)((uint32_t)pb.w >> 6) - kPackBias, 0, 0, 0);
+            } else {
+                const int e = q - kn, k = e >> 2, ty = e & 3;
+                const int4 pa = c.posA[i0 + k];
+                const int2 rc = c.posC[i0 + k];
+                const TE *src = ty == 0 ? tct + (size_t)pa.y * Rs
+                              : ty == 1 ? tct + (size_t)pa.w * Rs
+                              : ty == 2 ? tcr + (size_t)rc.x * Cg : tcr + (size_t)rc.y * Cg;
+                tab[e] = (uint64_t)(uintptr_t)src;
+            }
         }
         __syncthreads();
-        if (tid < kn) {
+        for (int q = tid; q < kn; q += nthr) {
             // the block's vehicles in order (positions are route-ordered) and each mission's slot
-            const int r = (int)((uint32_t)mi[tid].x >> 16);
+            const int r = (int)((uint32_t)mi[q].x >> 16);
             int slot = 0;
-            for (int k = 1; k <= tid; ++k) slot += ((uint32_t)mi[k].x >> 16) != ((uint32_t)mi[k - 1].x >> 16) ? 1 : 0;
-            mi2[tid].y = slot;
-            if (tid == 0 || ((uint32_t)mi[tid - 1].x >> 16) != (uint32_t)r) rl[slot] = r;
-            if (tid == kn - 1) rl[kGlobalKMax] = slot + 1;
+            for (int k = 1; k <= q; ++k) slot += ((uint32_t)mi[k].x >> 16) != ((uint32_t)mi[k - 1].x >> 16) ? 1 : 0;
+            mi2[q].y = slot;
+            if (q == 0 || ((uint32_t)mi[q - 1].x >> 16) != (uint32_t)r) rl[slot] = r;
+            if (q == kn - 1) rl[K] = slot + 1;
         }
         __syncthreads();
-        const int nd = rl[kGlobalKMax];
-        // one pass of loads: the pickup and successor columns (16-byte chunks of the
-        // transposed block), the delivery and predecessor rows (4-byte words of the
-        // block), the missions' tabu columns (kn x V entries)
+        const int nd = rl[K];
+        // one pass of loads: the four travel vectors of every mission (16-byte
+        // chunks) and the missions' tabu columns (kn x V entries)
         {
-            const int nA = 2 * kn * R16, nB = nA + 2 * kn * Cw, nC = nB + kn * V;
+            const int nA = 2 * kn * R16, nB = nA + 2 * kn * C16, nC = nB + kn * V;
             char *lds = (char *)vec;
             for (int b0 = tid; b0 < nC; b0 += UL * nthr) {
                 uint4 val[UL];
@@ -943,20 +952,20 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
                     const int it = b0 + u * nthr;
-                    kind[u] = it < nA ? 0 : it < nB ? 1 : it < nC ? 2 : 3;
+                    kind[u] = it < nB ? 0 : it < nC ? 1 : 2;
                     dst[u] = 0;
                     val[u] = make_uint4(0u, 0u, 0u, 0u);
-                    if (kind[u] == 0) {
+                    if (it < nA) {
                         const int v = it / R16, o = it - v * R16;
                         const int k = v >> 1, ty = v & 1;
                         val[u] = ((const uint4 *)(uintptr_t)tab[4 * k + ty])[o];
                         dst[u] = (k * per + ty * Re) * ES + 16 * o;
-                    } else if (kind[u] == 1) {
-                        const int e = it - nA, v = e / Cw, o = e - v * Cw;
+                    } else if (it < nB) {
+                        const int e = it - nA, v = e / C16, o = e - v * C16;
                         const int k = v >> 1, ty = v & 1;
-                        val[u].x = ((const uint32_t *)(uintptr_t)tab[4 * k + 2 + ty])[o];
-                        dst[u] = (k * per + 2 * Re + ty * Ce) * ES + 4 * o;
-                    } else if (kind[u] == 2) {
+                        val[u] = ((const uint4 *)(uintptr_t)tab[4 * k + 2 + ty])[o];
+                        dst[u] = (k * per + 2 * Re + ty * Ce) * ES + 16 * o;
+                    } else if (it < nC) {
                         const int e = it - nB, k = e / V, r = e - k * V;
                         val[u].x = (uint32_t)tabu[(size_t)r * M + (mi[k].x & 0xFFFF)];
                         dst[u] = e;
@@ -965,8 +974,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
                     if (kind[u] == 0) *(uint4 *)(lds + dst[u]) = val[u];
-                    else if (kind[u] == 1) *(uint32_t *)(lds + dst[u]) = val[u].x;
-                    else if (kind[u] == 2) trow[dst[u]] = (TB)val[u].x;
+                    else if (kind[u] == 1) trow[dst[u]] = (TB)val[u].x;
                 }
             }
         }
@@ -996,43 +1004,43 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         __syncthreads();
         // relocates: every gap against the block's missions
-        for (int b0 = tid; b0 < NG; b0 += UR * nthr) {
-            const int rb = b0 - tid;                      // first column of the round
-            const bool tail = rb + UR * nthr > NG;
+        for (int b0 = qr; b0 < NG; b0 += UR * QR) {
+            const int rb = b0 - qr;                       // first column of the round
+            const bool tail = rb + UR * QR > NG;
             int4 g[UR];
 #pragma unroll
             for (int u = 0; u < UR; ++u) {
-                const int G = b0 + u * nthr;
+                const int G = b0 + u * QR;
                 g[u] = c.gap[G < NG ? G : 0];
             }
-            for (int k = 0; k < kn; ++k) {
+            for (int k = pr; k < kn; k += PR) {
                 const int4 q = mi[k];
                 const TE *v = vec + k * per;
                 const TB *tr = trow + k * V;
                 uint32_t mn = 0xFFFFFFFFu;
-                if (!tail && (q.z + 1 < rb || q.z >= rb + UR * nthr)) {
+                if (!tail && (q.z + 1 < rb || q.z >= rb + UR * QR)) {
 #pragma unroll
                     for (int u = 0; u < UR; ++u) {
                         const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
                         const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
-                        const bool blk = (int)tr[gr] > th && !(d < thr);
+                        const bool blk = ((int)tr[gr] > th) & !(d < thr);
                         const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
                         mn = min(mn, key);
                     }
                 } else {
 #pragma unroll
                     for (int u = 0; u < UR; ++u) {
-                        const int G = b0 + u * nthr;
+                        const int G = b0 + u * QR;
                         const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
                         const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
-                        const bool blk = (int)tr[gr] > th && !(d < thr);
+                        const bool blk = ((int)tr[gr] > th) & !(d < thr);
                         const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
-                        const bool skip = G >= NG || (unsigned)(G - q.z) < 2u;
+                        const bool skip = (G >= NG) | ((unsigned)(G - q.z) < 2u);
                         mn = skip ? mn : min(mn, key);
                     }
                 }
                 if (mn != 0xFFFFFFFFu) {
-                    const int G = b0 + (int)(mn & 31u) * nthr;
+                    const int G = b0 + (int)(mn & 31u) * QR;
                     const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
                     best = umin64(best, pack_key((mn >> 31) != 0, d,
                                                  (uint32_t)(q.x & 0xFFFF) * (uint32_t)NG + (uint32_t)G));
@@ -1041,15 +1049,18 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         // swaps: every later position against the block's missions
         const int j0 = i0 + 1;
-        for (int b0 = j0 + tid; b0 < M; b0 += US * nthr) {
-            const int rb = b0 - tid;
-            const bool tail = rb + US * nthr > M;
+        int QS = kWave;
+        while (QS < nthr && QS * US < M - j0) QS <<= 1;
+        const int PS = nthr / QS, ps = tid / QS, qs = tid - ps * QS;
+        for (int b0 = j0 + qs; b0 < M; b0 += US * QS) {
+            const int rb = b0 - qs;
+            const bool tail = rb + US * QS > M;
             int4 a[US], b[US];
             int2 rc[US];
             int mj[US], rk[US];
 #pragma unroll
             for (int u = 0; u < US; ++u) {
-                const int j = b0 + u * nthr < M ? b0 + u * nthr : j0;
+                const int j = b0 + u * QS < M ? b0 + u * QS : j0;
                 a[u] = c.posA[j];
                 b[u] = c.posB[j];
                 rc[u] = c.posC[j];
@@ -1058,7 +1069,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
             // (swap indices of one mission grow with the partner's mission)
 #pragma unroll
             for (int u = 0; u < US; ++u)
-                mj[u] = b0 + u * nthr < M ? (b[u].z & 0xFFFF) : 0x10000 + u;
+                mj[u] = b0 + u * QS < M ? (b[u].z & 0xFFFF) : 0x10000 + u;
 #pragma unroll
             for (int u = 0; u < US; ++u) {
                 int r = 0;
@@ -1066,7 +1077,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 for (int w = 0; w < US; ++w) r += (w != u && mj[w] < mj[u]) ? 1 : 0;
                 rk[u] = r;
             }
-            for (int k = 0; k < kn; ++k) {
+            for (int k = ps; k < kn; k += PS) {
                 const int4 q = mi[k];
                 const int4 q2 = mi2[k];
                 const int mk = q.x & 0xFFFF, rkk = (int)((uint32_t)q.x >> 16);
@@ -1082,23 +1093,23 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                         const int d = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
                                     + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0);
-                        const uint32_t key = ((tb && !(d < thr)) ? 0x80000000u : 0u)
+                        const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
                                            | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
                         mn = min(mn, key);
                     }
                 } else {
 #pragma unroll
                     for (int u = 0; u < US; ++u) {
-                        const int j = b0 + u * nthr;
+                        const int j = b0 + u * QS;
                         const int rj = (int)((uint32_t)b[u].z >> 16);
                         const int m2 = mj[u] & 0xFFFF;
                         const int dg = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
                                      + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
                         const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0);
-                        const uint32_t key = ((tb && !(d < thr)) ? 0x80000000u : 0u)
+                        const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
                                            | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
-                        mn = (j >= M || j <= jk) ? mn : min(mn, key);
+                        mn = ((j >= M) | (j <= jk)) ? mn : min(mn, key);
                     }
                 }
                 if (mn != 0xFFFFFFFFu) {
@@ -1175,8 +1186,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, tabu, smem, red + 128, J.gk, wg, nwg,
-                                         t, thr, use_tabu);
+        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, tabu, smem, J.gk,
+                                         wg, nwg, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
         __syncthreads();

@@ -71,6 +71,8 @@ struct Request {
     SolveState *st = nullptr;
     at_result out{};                  // device arrays in mem
     InstDev host_inst{};
+    SolveState st_host{};             // upload sources: stay valid until the copies ran
+    GlobalBufs gb_host{};
     JobHost job;
     int t = 0;
     bool admitted = false, done = false;
@@ -147,31 +149,50 @@ struct Server {
         return st;
     }
 
-    int admit(Request &r)
+    // Admit a batch of requests whose arena blocks are allocated: upload their
+    // state tables, prepare every instance (one stream synchronisation for the
+    // batch), plan their solves.  A request that fails is finished with its
+    // error status and its memory released; the others are returned in `ok`.
+    void admit_batch(const std::vector<Request *> &batch, std::vector<Request *> &ok)
     {
-        const SolveState st = carve(r);
-        // state table: pointers, valid = 0 (the first chunk starts from the greedy solution);
-        // prepare_instances below synchronises the stream before `st` goes out of scope
-        hipError_t e = hipMemcpyAsync(r.st, &st, sizeof(SolveState), hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return hip_fail(e, "server: state upload");
-        std::vector<InstDev> ih(1, r.host_inst);
-        int rc = prepare_instances(1, r.dinst, ih, s);
-        if (rc) return rc;
-        r.host_inst = ih[0];
-        r.job.inst = 0;
-        r.job.pr = r.pr;
-        r.job.pr.schedule = r.pr.schedule == AT_SCHED_MULTI ? AT_SCHED_AUTO : r.pr.schedule;
-        r.job.seed = r.pr.restart_seed;
-        rc = plan_job(r.job, r.host_inst, false);
-        if (rc) return rc;
-        if (r.job.kind == AT_SCHED_GLOBAL) {
-            std::vector<JobHost> one(1, r.job);
-            rc = upload_gstates(one, ih, s);
-            if (rc) return rc;
+        std::vector<int> rc(batch.size(), AT_OK);
+        for (size_t k = 0; k < batch.size(); ++k) {
+            Request &r = *batch[k];
+            // state table: pointers, valid = 0 (the first chunk starts from the greedy solution)
+            r.st_host = carve(r);
+            hipError_t e = hipMemcpyAsync(r.st, &r.st_host, sizeof(SolveState), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) { rc[k] = hip_fail(e, "server: state upload"); continue; }
+            rc[k] = prepare_enqueue(1, r.dinst, &r.host_inst, s);
         }
-        r.admitted = true;
-        r.t = 0;
-        return AT_OK;
+        hipError_t e = hipStreamSynchronize(s);
+        for (size_t k = 0; k < batch.size(); ++k) {
+            Request &r = *batch[k];
+            if (rc[k] == AT_OK && e != hipSuccess) rc[k] = hip_fail(e, "server: prepare");
+            if (rc[k] == AT_OK) rc[k] = prepare_check(1, &r.host_inst);
+            if (rc[k] == AT_OK) {
+                r.job.inst = 0;
+                r.job.pr = r.pr;
+                r.job.pr.schedule = r.pr.schedule == AT_SCHED_MULTI ? AT_SCHED_AUTO : r.pr.schedule;
+                r.job.seed = r.pr.restart_seed;
+                rc[k] = plan_job(r.job, r.host_inst, false);
+            }
+            if (rc[k] == AT_OK && r.job.kind == AT_SCHED_GLOBAL) {
+                carve_gstate(r.gb_host, r.host_inst.M, r.host_inst.V, r.job.tb16 ? 2 : 4, (char *)r.job.gstate);
+                const hipError_t u = hipMemcpyAsync(r.job.gstate, &r.gb_host, sizeof(GlobalBufs),
+                                                    hipMemcpyHostToDevice, s);
+                if (u != hipSuccess) rc[k] = hip_fail(u, "server: state tables");
+            }
+            if (rc[k] != AT_OK) {
+                r.done = true;
+                r.last.status = rc[k];
+                arena.release(r.mem, r.bytes);
+                r.mem = nullptr;
+                continue;
+            }
+            r.admitted = true;
+            r.t = 0;
+            ok.push_back(&r);
+        }
     }
 
     // Retire finished solves after the last launch completed.
@@ -305,21 +326,15 @@ int at_server_progress(void *server, int32_t *n_active)
         if (rc) return rc;
     }
     // admit in arrival order while a slot and memory are free
-    while (!sv->waiting.empty() && (int)sv->active.size() < sv->max_slots) {
+    std::vector<Request *> batch;
+    while (!sv->waiting.empty() && (int)(sv->active.size() + batch.size()) < sv->max_slots) {
         Request *r = sv->waiting.front();
         r->mem = sv->arena.alloc(r->bytes);
         if (!r->mem) break;
         sv->waiting.pop_front();
-        int rc = sv->admit(*r);
-        if (rc) {
-            r->done = true;
-            r->last.status = rc;
-            sv->arena.release(r->mem, r->bytes);
-            r->mem = nullptr;
-            continue;
-        }
-        sv->active.push_back(r);
+        batch.push_back(r);
     }
+    if (!batch.empty()) sv->admit_batch(batch, sv->active);
     int rc = sv->launch();
     if (n_active) *n_active = (int32_t)(sv->active.size() + sv->waiting.size());
     return rc;
