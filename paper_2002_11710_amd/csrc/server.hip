@@ -25,6 +25,11 @@ namespace at {
 
 namespace {
 
+// Move slots per iteration of the reference solve for chunk lengths: a
+// one-workgroup solve with S slots runs max(1, kChunkSlots / S) chunks' worth
+// of iterations per launch.
+constexpr int64_t kChunkSlots = 1 << 18;
+
 struct Arena {
     char *base = nullptr;
     size_t size = 0;
@@ -67,7 +72,8 @@ struct Request {
     char *mem = nullptr;
     // carved from mem
     InstDev *dinst = nullptr;
-    JobScal *scal = nullptr;
+    JobScal *scal = nullptr;          // the server's result slot `slot`
+    int slot = -1;
     SolveState *st = nullptr;
     at_result out{};                  // device arrays in mem
     InstDev host_inst{};
@@ -82,7 +88,7 @@ struct Request {
 size_t request_bytes(const at_instance &in, const at_params &pr)
 {
     const size_t M = (size_t)in.n_missions, V = (size_t)in.n_vehicles;
-    size_t b = al256(sizeof(InstDev)) + al256(sizeof(JobScal)) + al256(sizeof(SolveState));
+    size_t b = al256(sizeof(InstDev)) + al256(sizeof(SolveState));
     b += inst_bytes(in, may_need_global(in, pr));
     b += al256(4 * M) + al256(4 * (V + 1)) + al256(4 * M * V);          // saved routes + tabu
     b += al256(4 * (V + 1)) + 2 * al256(4 * (M ? M : 1));                // best routes
@@ -104,6 +110,9 @@ struct Server {
     Arena arena;
     JobDev *djobs = nullptr;
     Xchg *xs = nullptr;
+    JobScal *dscal = nullptr;         // per-slot results, read back with one copy per chunk
+    std::vector<JobScal> hscal;
+    std::vector<int> free_slots;
     hipEvent_t done_ev = nullptr;
     bool in_flight = false;
     uint64_t next_ticket = 1;
@@ -126,7 +135,6 @@ struct Server {
         char *p = r.mem;
         const size_t M = (size_t)r.inst.n_missions, V = (size_t)r.inst.n_vehicles;
         r.dinst = (InstDev *)p; p += al256(sizeof(InstDev));
-        r.scal = (JobScal *)p; p += al256(sizeof(JobScal));
         r.st = (SolveState *)p; p += al256(sizeof(SolveState));
         const bool with_t = may_need_global(r.inst, r.pr);
         carve_inst(r.host_inst, r.inst, p, with_t); p += inst_bytes(r.inst, with_t);
@@ -158,6 +166,9 @@ struct Server {
         std::vector<int> rc(batch.size(), AT_OK);
         for (size_t k = 0; k < batch.size(); ++k) {
             Request &r = *batch[k];
+            r.slot = free_slots.back();
+            free_slots.pop_back();
+            r.scal = dscal + r.slot;
             // state table: pointers, valid = 0 (the first chunk starts from the greedy solution)
             r.st_host = carve(r);
             hipError_t e = hipMemcpyAsync(r.st, &r.st_host, sizeof(SolveState), hipMemcpyHostToDevice, s);
@@ -187,6 +198,8 @@ struct Server {
                 r.last.status = rc[k];
                 arena.release(r.mem, r.bytes);
                 r.mem = nullptr;
+                free_slots.push_back(r.slot);
+                r.slot = -1;
                 continue;
             }
             r.admitted = true;
@@ -199,20 +212,21 @@ struct Server {
     int collect()
     {
         if (active.empty()) return AT_OK;
-        std::vector<JobScal> hs(active.size());
-        for (size_t k = 0; k < active.size(); ++k) {
-            hipError_t e = hipMemcpyAsync(&hs[k], active[k]->scal, sizeof(JobScal), hipMemcpyDeviceToHost, s);
-            if (e != hipSuccess) return hip_fail(e, "server: read back");
-        }
-        hipError_t e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "server: chunk");
+        hipError_t e = hipMemcpyAsync(hscal.data(), dscal, sizeof(JobScal) * hscal.size(), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "server: read back");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "server: chunk");
         std::vector<Request *> keep;
-        for (size_t k = 0; k < active.size(); ++k) {
-            Request *r = active[k];
-            r->last = hs[k];
-            r->t = hs[k].iters_done;
-            if (hs[k].status != AT_OK || hs[k].stopped || r->t >= r->pr.max_iters) r->done = true;
-            else keep.push_back(r);
+        for (Request *r : active) {
+            const JobScal &h = hscal[(size_t)r->slot];
+            r->last = h;
+            r->t = h.iters_done;
+            if (h.status != AT_OK || h.stopped || r->t >= r->pr.max_iters) {
+                r->done = true;
+                free_slots.push_back(r->slot);
+                r->slot = -1;
+            } else {
+                keep.push_back(r);
+            }
         }
         active.swap(keep);
         return AT_OK;
@@ -238,8 +252,14 @@ struct Server {
             Request *r = active[(size_t)order[k]];
             int rc = fill_job(hj[k], jobs[(size_t)order[k]], r->dinst, r->scal);
             if (rc) return rc;
+            // a one-workgroup solve with few move slots runs proportionally more
+            // iterations per chunk (up to all that remain): small requests finish
+            // in the chunk they were admitted in instead of waiting out the large ones
+            const JobHost &h = jobs[(size_t)order[k]];
+            int64_t it = chunk;
+            if (h.kind == AT_SCHED_WG) it *= std::max<int64_t>(1, kChunkSlots / std::max<int64_t>(1, h.slots));
             hj[k].t_begin = r->t;
-            hj[k].t_end = std::min(r->pr.max_iters, r->t + chunk);
+            hj[k].t_end = (int)std::min<int64_t>(r->pr.max_iters, r->t + it);
             hj[k].resume = 1;
             hj[k].save = 1;
             hj[k].st = r->st;
@@ -269,7 +289,8 @@ int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_i
     if (!server) return fail(AT_EINVAL, "null server handle");
     if (max_slots < 1 || max_slots > 65536) return fail(AT_EINVAL, "max_slots outside [1, 65536]");
     if (chunk_iters < 1) return fail(AT_EINVAL, "chunk_iters must be positive");
-    const size_t fixed = al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots);
+    const size_t fixed = al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots)
+                       + al256(sizeof(JobScal) * (size_t)max_slots);
     if (hbm_budget_bytes < fixed + (1 << 20)) return fail(AT_ENOMEM, "budget too small");
     Server *sv = new Server();
     sv->s = (hipStream_t)stream;
@@ -280,6 +301,9 @@ int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_i
     if (e != hipSuccess) { delete sv; return hip_fail(e, "server arena"); }
     sv->xs = (Xchg *)sv->dev;
     sv->djobs = (JobDev *)(sv->dev + al256(sizeof(Xchg)));
+    sv->dscal = (JobScal *)(sv->dev + al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots));
+    sv->hscal.assign((size_t)max_slots, JobScal{});
+    for (int k = max_slots - 1; k >= 0; --k) sv->free_slots.push_back(k);
     sv->arena.init(sv->dev + fixed, hbm_budget_bytes - fixed);
     if ((e = hipEventCreateWithFlags(&sv->done_ev, hipEventDisableTiming)) != hipSuccess) {
         delete sv;
