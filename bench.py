@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--stress", type=int, default=0,
                     help="also run the 256 x 10000 stress instance for this many iterations (Tabu and NS)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain per-instance comparisons (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--schedule", type=int, default=0)
@@ -199,21 +201,21 @@ def main():
                      "lds_GBps": lds_bytes / (tabu_launch_ms / 1000.0) / 1e9},
     }
     if args.batch:
-        line["batch"] = bench_batch(args.batch)
+        line["batch"] = bench_batch(args.batch, plain=not args.no_plain)
     if args.stress:
         line["stress"] = bench_stress(args.stress)
     if args.serve:
         rates = [float(x) for x in args.serve.split(",")]
         line["serving"] = [bench_serve(lam, args.serve_requests, chunk=args.serve_chunk,
                                        slots=args.serve_slots,
-                                       plain_sample=32 if k == len(rates) - 1 else 0)
+                                       plain_sample=32 if k == len(rates) - 1 and not args.no_plain else 0)
                            for k, lam in enumerate(rates)]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(line))
 
 
-def bench_batch(n_inst: int, restarts: int = 8):
+def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     """Uneven batch: n_inst instances x restarts restarts, 2000 iterations each, one call."""
     import numpy as np
     import torch
@@ -245,6 +247,12 @@ def bench_batch(n_inst: int, restarts: int = 8):
         ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
     kms = float(res[0]["search_ms"])
     assert all(r["status"] == 0 for r in res)
+    out = {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
+           "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
+           "move_evals_per_s": evals / wall, "search_ms": kms,
+           "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS}
+    if not plain:
+        return out
     # the plain per-instance form: one at_solve launch per (instance, restart), in
     # sequence on one stream, on a sample of the same solves (identical results)
     from gen.instances import restart_seed
@@ -265,13 +273,10 @@ def bench_batch(n_inst: int, restarts: int = 8):
     # plain solves/s for this batch's mix: the sample's move-eval rate applied to all solves
     plain_evals_per_s = plain_work * 2000 / t_plain
     plain_sps = plain_evals_per_s / (all_work * 2000 / len(res))
-    return {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
-            "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
-            "move_evals_per_s": evals / wall, "search_ms": kms,
-            "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS,
-            "plain_sample_solves": n_plain, "plain_sample_s": t_plain,
-            "plain_solves_per_s": plain_sps,
-            "speedup_vs_plain": (n_inst * restarts / wall) / plain_sps}
+    out.update({"plain_sample_solves": n_plain, "plain_sample_s": t_plain,
+                "plain_solves_per_s": plain_sps,
+                "speedup_vs_plain": (n_inst * restarts / wall) / plain_sps})
+    return out
 
 
 def bench_stress(iters: int):

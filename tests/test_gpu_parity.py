@@ -10,7 +10,7 @@ import pytest
 import oracle
 from gen.instances import (batch_instance, batch_specs, brute_twin, m400_instance, make_instance,
                            restart_seed, small_instance, stress_instance)
-from helpers import assert_same_result, oracle_solve
+from helpers import assert_same_result, gpu_to_np, oracle_solve
 
 pytestmark = pytest.mark.gpu
 
@@ -248,3 +248,32 @@ def test_stress_instance_prefix():
     _, o = oracle_solve(inst, tenure=25, iters=iters)
     g = at.solve(_dev(inst), tenure=25, iters=iters)
     assert_same_result(o, g, "256x10000 prefix")
+
+
+def test_batch_mixed_schedules():
+    """One batch call with instances too large for LDS (HBM-resident schedule,
+    sharing a cooperative launch) and small ones (one workgroup each): every
+    solve equals its oracle run."""
+    insts = [make_instance(500 + k, 750, 13, 25, 500) for k in range(2)]
+    insts += [make_instance(510 + k, 40, 3, 4, 25 + 5 * k) for k in range(4)]
+    devs = [_dev(i) for i in insts]
+    params = [at._capi.make_params(at.AT_TABU, 7, 50, True, 0, True) for _ in insts]
+    res = at.solve_batch(devs, params, 2)
+    from gen.instances import restart_seed
+    for k, inst in enumerate(insts):
+        for r in range(2):
+            _, o = oracle_solve(inst, tenure=7, iters=50, restart_seed=restart_seed(0, r))
+            assert_same_result(o, res[k * 2 + r], f"batch instance {k} restart {r}")
+
+
+def test_global_shared_launch_partition():
+    """More global-schedule solves than the launch can give their requested
+    workgroups: shares are cut proportionally; each result equals the solve alone."""
+    insts = [make_instance(600 + k, 60, 4, 6, 45 + 3 * k) for k in range(12)]
+    devs = [_dev(i) for i in insts]
+    params = [at._capi.make_params(at.AT_TABU, 5, 40, True, 0, True, at.SCHED_GLOBAL, 64) for _ in insts]
+    res = at.solve_batch(devs, params, 1)
+    for k, d in enumerate(devs):
+        alone = at.solve(d, tenure=5, iters=40, schedule=at.SCHED_GLOBAL, n_groups=3)
+        assert np.array_equal(gpu_to_np(res[k])["tr_move"], gpu_to_np(alone)["tr_move"]), k
+        assert res[k]["best_obj"] == alone["best_obj"], k

@@ -124,3 +124,23 @@ def test_serving_stream_sample():
     for k, t in enumerate(tickets):
         _same(alone[k], got[t], f"stream request M={chosen[k]['n_missions']}")
     srv.close()
+
+
+def test_mix_with_hbm_resident_requests():
+    """Requests too large for one workgroup's LDS (HBM-resident schedule, sharing
+    one cooperative launch with per-request workgroup ranges) next to small
+    ones: each result equals the request alone, under two chunkings."""
+    big = [make_instance(400 + k, 750, 13, 25, 500) for k in range(2)]
+    reqs = [(i, dict(variant=at.AT_TABU, tenure=9, iters=60, restart_seed=0, trace=True)) for i in big]
+    reqs += _requests()[:3]
+    devs = [_dev(i) for i, _ in reqs]
+    alone = [at.solve(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    for chunk in (5, 64):
+        srv = at.Server(1 << 30, max_slots=8, chunk_iters=chunk)
+        tickets = [srv.submit(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+        got = _drive(srv, list(tickets))
+        for k, t in enumerate(tickets):
+            _same(alone[k], got[t], f"request {k} chunk {chunk}")
+        srv.close()
+    _, o = oracle_solve(big[0], tenure=9, iters=60)
+    assert_same_result(o, alone[0], "large request alone vs oracle")
