@@ -124,7 +124,6 @@ void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
 
 void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
 {
-    (void)tbsz;
     auto a = [](uint64_t x) { return (size_t)((x + 255u) & ~(uint64_t)255u); };
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V;
     size_t o = al256(sizeof(GlobalBufs));
@@ -142,6 +141,8 @@ void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
         g.posC[k] = (int2 *)(base + o); o += a(8 * uM);
     }
     g.tabu = (void *)(base + o);
+    o += a((uint64_t)tbsz * uM * uV);
+    g.tabu_t = (void *)(base + o);
     g.cur = 0;
     g.pad = 0;
     g.key[0] = g.key[1] = g.key[2] = kKeyNone;
@@ -526,12 +527,42 @@ int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
             const int b = std::min(e, a + cap);
             int64_t want = 0;
             for (int q = a; q < b; ++q) want += jobs[(size_t)order[(size_t)q]].groups;
+            if (want > cap) {
+                // water-filling by work (move slots x iterations of this launch): shares
+                // proportional to work, none above what the job asked for, at least one
+                std::vector<int64_t> w((size_t)(b - a));
+                std::vector<int> give((size_t)(b - a), 0);
+                for (int q = a; q < b; ++q) {
+                    const JobHost &h = jobs[(size_t)order[(size_t)q]];
+                    w[(size_t)(q - a)] = std::max<int64_t>(1, h.slots * std::max<int64_t>(1, h.iters));
+                }
+                int64_t left = cap;
+                for (bool capped = true; capped;) {
+                    capped = false;
+                    double tw = 0.0;
+                    for (int q = a; q < b; ++q) if (!give[(size_t)(q - a)]) tw += (double)w[(size_t)(q - a)];
+                    for (int q = a; q < b && tw > 0.0; ++q) {
+                        if (give[(size_t)(q - a)]) continue;
+                        const int cap_q = jobs[(size_t)order[(size_t)q]].groups;
+                        if ((double)w[(size_t)(q - a)] * (double)left / tw >= (double)cap_q) {
+                            give[(size_t)(q - a)] = cap_q;
+                            left -= cap_q;
+                            capped = true;
+                            break;
+                        }
+                    }
+                }
+                double tw = 0.0;
+                for (int q = a; q < b; ++q) if (!give[(size_t)(q - a)]) tw += (double)w[(size_t)(q - a)];
+                for (int q = a; q < b; ++q)
+                    if (!give[(size_t)(q - a)])
+                        give[(size_t)(q - a)] = std::max(1, (int)((double)w[(size_t)(q - a)] * (double)left / tw));
+                for (int q = a; q < b; ++q) jobs[(size_t)order[(size_t)q]].groups = give[(size_t)(q - a)];
+            }
             int g0 = 0;
             for (int q = a; q < b; ++q) {
                 JobHost &h = jobs[(size_t)order[(size_t)q]];
-                int g = h.groups;
-                if (want > cap) g = std::max<int>(1, (int)((int64_t)h.groups * cap / want));
-                g = std::min(g, cap - g0 - (b - q - 1));   // leave one for each later job
+                int g = std::min(h.groups, cap - g0 - (b - q - 1));   // leave one for each later job
                 h.groups = std::max(1, g);
                 h.g0 = g0;
                 h.launch = launch;
@@ -569,6 +600,7 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
     for (auto &h : jobs) {
         int rc = plan_job(h, ih[(size_t)h.inst], n == 1);
         if (rc) return rc;
+        h.iters = h.pr.max_iters;
     }
     int rc = upload_gstates(jobs, ih, s);
     if (rc) return rc;

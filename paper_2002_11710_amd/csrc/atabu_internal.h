@@ -97,7 +97,8 @@ struct GlobalBufs {
     int32_t *off[2];
     int4 *posA[2], *posB[2], *gap[2];
     int2 *posC[2];                    // per position: exit row of its delivery, of its predecessor
-    void *tabu;
+    void *tabu;                       // [vehicle][mission] expiry table
+    void *tabu_t;                     // the same table mission-major ([mission][vehicle])
     int32_t cur;                      // which parity holds the current routes
     int32_t pad;
     // exchange of the solve's workgroups (cleared before every launch), on its own cache lines
@@ -200,7 +201,7 @@ __host__ __device__ inline uint64_t global_state_bytes(int M, int V, int tbsz)
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V, NG = uM + uV;
     auto a = [](uint64_t x) { return (x + 255u) & ~(uint64_t)255u; };
     return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * (2 * a(16 * uM) + a(16 * NG) + a(8 * uM))
-         + a((uint64_t)tbsz * uM * uV);
+         + 2 * a((uint64_t)tbsz * uM * uV);
 }
 
 __host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M + V) + M * (M - 1) / 2; }

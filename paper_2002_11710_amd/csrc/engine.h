@@ -24,6 +24,7 @@ struct JobHost {
     uint64_t seed = 0;
     at_result out{};
     int64_t slots = 0;
+    int64_t iters = 0;                // iterations this launch runs (weights shared launches)
     uint32_t lds = 0;
     int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL

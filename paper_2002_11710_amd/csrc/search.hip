@@ -51,6 +51,52 @@ struct Ctx {
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// Global-memory views of a pointer: accesses through them compile to global_*
+// instructions, which count on the vector-memory counter only.  The flat
+// instructions a generic pointer gets also hold the LDS counter, so every LDS
+// wait would also wait for the HBM accesses in flight.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int4 gld4(const int4 *p, size_t i)
+{
+    const v4i_t x = ((const __attribute__((address_space(1))) v4i_t *)p)[i];
+    return make_int4(x.x, x.y, x.z, x.w);
+}
+__device__ __forceinline__ int2 gld2(const int2 *p, size_t i)
+{
+    const v2i_t x = ((const __attribute__((address_space(1))) v2i_t *)p)[i];
+    return make_int2(x.x, x.y);
+}
+__device__ __forceinline__ void gst4(int4 *p, size_t i, int4 v)
+{
+    v4i_t x;
+    x.x = v.x; x.y = v.y; x.z = v.z; x.w = v.w;
+    ((__attribute__((address_space(1))) v4i_t *)p)[i] = x;
+}
+__device__ __forceinline__ void gst2(int2 *p, size_t i, int2 v)
+{
+    v2i_t x;
+    x.x = v.x; x.y = v.y;
+    ((__attribute__((address_space(1))) v2i_t *)p)[i] = x;
+}
+// 16 bytes at a global address held as an integer
+__device__ __forceinline__ uint4 gld16(uint64_t addr, int o)
+{
+    typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
+    const v4u_t x = ((const __attribute__((address_space(1))) v4u_t *)addr)[o];
+    return make_uint4(x.x, x.y, x.z, x.w);
+}
+
 __device__ __forceinline__ uint64_t wave_min(uint64_t k)
 {
 #pragma unroll
@@ -782,27 +828,27 @@ __device__ __forceinline__ int next_seq(const Ctx &o, const GMove &mv, int k)
 {
     if (mv.kind == 1) {
         if (k == mv.q) return mv.m;
-        return o.seq[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
+        return gld(o.seq)[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
     }
     if (mv.kind == 2) {
         if (k == mv.s1) return mv.m2;
         if (k == mv.s2) return mv.m1;
     }
-    return o.seq[k];
+    return gld(o.seq)[k];
 }
 
 __device__ __forceinline__ int next_rt(const Ctx &o, const GMove &mv, int k)
 {
     if (mv.kind == 1) {
         if (k == mv.q) return mv.v;
-        return o.rt[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
+        return gld(o.rt)[(k >= mv.lo && k <= mv.hi) ? k + mv.dir : k];
     }
-    return o.rt[k];
+    return gld(o.rt)[k];
 }
 
 __device__ __forceinline__ int next_off(const Ctx &o, const GMove &mv, int r)
 {
-    int x = o.off[r];
+    int x = gld(o.off)[r];
     if (mv.kind == 1) {
         if (mv.v > mv.rs && r > mv.rs && r <= mv.v) x -= 1;
         if (mv.v < mv.rs && r > mv.v && r <= mv.rs) x += 1;
@@ -829,38 +875,38 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
         const int sn2 = i + 2 < M ? next_seq(o, mv, i + 2) : 0;
         const int o0 = next_off(o, mv, r), o1 = next_off(o, mv, r + 1);
         const bool first = i == o0, last = i + 1 == o1;
-        const int x = first ? o.vrow[r] : o.mrow[sp];
-        const int y = last ? o.vcol[r] : o.mcol[sn];
-        const int mc = o.mcol[m], mr = o.mrow[m];
-        const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
+        const int x = first ? gld(o.vrow)[r] : gld(o.mrow)[sp];
+        const int y = last ? gld(o.vcol)[r] : gld(o.mcol)[sn];
+        const int mc = gld(o.mcol)[m], mr = gld(o.mrow)[m];
+        const int a = gld(tc)[x + mc], bb = gld(tc)[mr + y], l = gld(tc)[x + y];
         int adj = 0;
         if (!last) {
             // swapping m with its successor in the same route: P m n N -> P n m N
-            const int y2 = (i + 2 == o1) ? o.vcol[r] : o.mcol[sn2];
-            const int mrn = o.mrow[sn];
-            adj = l + (int)tc[mrn + mc] + (int)tc[mr + y2] - a - bb - (int)tc[mrn + y2];
+            const int y2 = (i + 2 == o1) ? gld(o.vcol)[r] : gld(o.mcol)[sn2];
+            const int mrn = gld(o.mrow)[sn];
+            adj = l + (int)gld(tc)[mrn + mc] + (int)gld(tc)[mr + y2] - a - bb - (int)gld(tc)[mrn + y2];
         }
-        n.posA[i] = make_int4(mr, mc, x, y);
-        n.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
-                              (int)((uint32_t)(adj + kPackBias) << 6));
-        n.gap[i + r] = make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
-        n.posC[i] = make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs));
+        gst4(n.posA, i, make_int4(mr, mc, x, y));
+        gst4(n.posB, i, make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
+                                  (int)((uint32_t)(adj + kPackBias) << 6)));
+        gst4(n.gap, i + r, make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16))));
+        gst2(n.posC, i, make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs)));
         if (write_routes) {
-            n.seq[i] = (uint16_t)m;
-            n.rt[i] = (uint16_t)r;
-            n.pof[m] = (uint16_t)i;
-            n.rof[m] = (uint16_t)r;
+            gst(n.seq)[i] = (uint16_t)m;
+            gst(n.rt)[i] = (uint16_t)r;
+            gst(n.pof)[m] = (uint16_t)i;
+            gst(n.rof)[m] = (uint16_t)r;
         }
     }
     for (int r = tid; r <= V; r += nthr) {
         const int o0 = next_off(o, mv, r);
-        if (write_routes) n.off[r] = o0;
+        if (write_routes) gst(n.off)[r] = o0;
         if (r == V) continue;
         // the gap after the route's last mission
         const int e = next_off(o, mv, r + 1);
-        const int x = (o0 == e) ? o.vrow[r] : o.mrow[next_seq(o, mv, e - 1)];
-        n.gap[e + r] = make_int4(x, o.vcol[r], (int)tc[x + o.vcol[r]],
-                                 (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        const int x = (o0 == e) ? gld(o.vrow)[r] : gld(o.mrow)[next_seq(o, mv, e - 1)];
+        gst4(n.gap, e + r, make_int4(x, gld(o.vcol)[r], (int)gld(tc)[x + gld(o.vcol)[r]],
+                                     (int)((uint32_t)r | (((uint32_t)x / Cs) << 16))));
     }
 }
 
@@ -882,8 +928,8 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
 // others skip the checks.
 template <typename TE, typename TB>
 __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
-                                const TE *tcr, const TB *tabu, char *smem, int K, int wg, int nwg,
-                                int t, int thr, bool use_tabu)
+                                const TE *tcr, const TB *tabu, const TB *tabu_t, char *smem, int K,
+                                int wg, int nwg, int t, int thr, bool use_tabu)
 {
     constexpr int UR = 8, US = 4, UL = 8;      // relocate, swap and staging loads in flight
     constexpr int ES = (int)sizeof(TE);
@@ -915,17 +961,24 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         __syncthreads();   // the previous block's LDS reads are done
         for (int q = tid; q < 5 * kn; q += nthr) {
             if (q < kn) {
-                const int4 pb = c.posB[i0 + q];
+                const int4 pb = gld4(c.posB, i0 + q);
                 const int r = (int)((uint32_t)pb.z >> 16);
                 mi[q] = make_int4(pb.z, pb.y - pb.x, i0 + q + r, pb.x);
                 mi2[q] = make_int4((int)((uint32_t)pb.w >> 6) - kPackBias, 0, 0, 0);
             } else {
+                // the successor column (Y) and predecessor row (X) of a mission whose
+                // neighbour in the route is also in the block are that neighbour's
+                // pickup column / delivery row: not loaded again
                 const int e = q - kn, k = e >> 2, ty = e & 3;
-                const int4 pa = c.posA[i0 + k];
-                const int2 rc = c.posC[i0 + k];
+                const int4 pa = gld4(c.posA, i0 + k);
+                const int2 rc = gld2(c.posC, i0 + k);
+                const uint32_t rk = (uint32_t)gld4(c.posB, i0 + k).z >> 16;
+                const bool same_next = k + 1 < kn && ((uint32_t)gld4(c.posB, i0 + k + 1).z >> 16) == rk;
+                const bool same_prev = k > 0 && ((uint32_t)gld4(c.posB, i0 + k - 1).z >> 16) == rk;
                 const TE *src = ty == 0 ? tct + (size_t)pa.y * Rs
-                              : ty == 1 ? tct + (size_t)pa.w * Rs
-                              : ty == 2 ? tcr + (size_t)rc.x * Cg : tcr + (size_t)rc.y * Cg;
+                              : ty == 1 ? (same_next ? nullptr : tct + (size_t)pa.w * Rs)
+                              : ty == 2 ? tcr + (size_t)rc.x * Cg
+                                        : (same_prev ? nullptr : tcr + (size_t)rc.y * Cg);
                 tab[e] = (uint64_t)(uintptr_t)src;
             }
         }
@@ -938,6 +991,11 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
             mi2[q].y = slot;
             if (q == 0 || ((uint32_t)mi[q - 1].x >> 16) != (uint32_t)r) rl[slot] = r;
             if (q == kn - 1) rl[K] = slot + 1;
+            // where the mission's predecessor row and successor column sit in LDS
+            const bool same_prev = q > 0 && ((uint32_t)mi[q - 1].x >> 16) == (uint32_t)r;
+            const bool same_next = q + 1 < kn && ((uint32_t)mi[q + 1].x >> 16) == (uint32_t)r;
+            mi2[q].z = same_prev ? (q - 1) * per + 2 * Re : q * per + 2 * Re + Ce;
+            mi2[q].w = same_next ? (q + 1) * per : q * per + Re;
         }
         __syncthreads();
         const int nd = rl[K];
@@ -945,6 +1003,14 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         // chunks) and the missions' tabu columns (kn x V entries)
         {
             const int nA = 2 * kn * R16, nB = nA + 2 * kn * C16, nC = nB + kn * V;
+            // quotients by multiply-high where it is exact (dividend x divisor < 2^32),
+            // else by division
+            const uint32_t mR = 0xFFFFFFFFu / (uint32_t)R16 + 1u, mC = 0xFFFFFFFFu / (uint32_t)C16 + 1u;
+            const uint32_t mV = 0xFFFFFFFFu / (uint32_t)V + 1u;
+            // (a divisor of 1 would need the multiplier 2^32: plain division there)
+            const bool fR = R16 > 1 && (uint64_t)nA * (uint64_t)R16 < (1ull << 32);
+            const bool fC = C16 > 1 && (uint64_t)(nB - nA) * (uint64_t)C16 < (1ull << 32);
+            const bool fV = V > 1 && (uint64_t)(nC - nB) * (uint64_t)V < (1ull << 32);
             char *lds = (char *)vec;
             for (int b0 = tid; b0 < nC; b0 += UL * nthr) {
                 uint4 val[UL];
@@ -956,18 +1022,22 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                     dst[u] = 0;
                     val[u] = make_uint4(0u, 0u, 0u, 0u);
                     if (it < nA) {
-                        const int v = it / R16, o = it - v * R16;
+                        const int v = fR ? (int)__umulhi((uint32_t)it, mR) : it / R16, o = it - v * R16;
                         const int k = v >> 1, ty = v & 1;
-                        val[u] = ((const uint4 *)(uintptr_t)tab[4 * k + ty])[o];
+                        const uint64_t sa = tab[4 * k + ty];
+                        if (sa) val[u] = gld16(sa, o);
+                        else kind[u] = 3;
                         dst[u] = (k * per + ty * Re) * ES + 16 * o;
                     } else if (it < nB) {
-                        const int e = it - nA, v = e / C16, o = e - v * C16;
+                        const int e = it - nA, v = fC ? (int)__umulhi((uint32_t)e, mC) : e / C16, o = e - v * C16;
                         const int k = v >> 1, ty = v & 1;
-                        val[u] = ((const uint4 *)(uintptr_t)tab[4 * k + 2 + ty])[o];
+                        const uint64_t sa = tab[4 * k + 2 + ty];
+                        if (sa) val[u] = gld16(sa, o);
+                        else kind[u] = 3;
                         dst[u] = (k * per + 2 * Re + ty * Ce) * ES + 16 * o;
                     } else if (it < nC) {
-                        const int e = it - nB, k = e / V, r = e - k * V;
-                        val[u].x = (uint32_t)tabu[(size_t)r * M + (mi[k].x & 0xFFFF)];
+                        const int e = it - nB, k = fV ? (int)__umulhi((uint32_t)e, mV) : e / V, r = e - k * V;
+                        val[u].x = (uint32_t)gld(tabu_t)[(size_t)(mi[k].x & 0xFFFF) * V + r];
                         dst[u] = e;
                     }
                 }
@@ -987,7 +1057,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 for (int u = 0; u < UL; ++u) {
                     const int ch = c0 + u * nwaves;
                     const int q = ch / Mc, m = (ch - q * Mc) * 64 + lane;
-                    val[u] = (ch < nch && m < M) ? tabu[(size_t)rl[q] * M + m] : (TB)0;
+                    val[u] = (ch < nch && m < M) ? gld(tabu)[(size_t)rl[q] * M + m] : (TB)0;
                 }
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
@@ -1011,7 +1081,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
             for (int u = 0; u < UR; ++u) {
                 const int G = b0 + u * QR;
-                g[u] = c.gap[G < NG ? G : 0];
+                g[u] = gld4(c.gap, G < NG ? G : 0);
             }
             for (int k = pr; k < kn; k += PR) {
                 const int4 q = mi[k];
@@ -1061,9 +1131,9 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
             for (int u = 0; u < US; ++u) {
                 const int j = b0 + u * QS < M ? b0 + u * QS : j0;
-                a[u] = c.posA[j];
-                b[u] = c.posB[j];
-                rc[u] = c.posC[j];
+                a[u] = gld4(c.posA, j);
+                b[u] = gld4(c.posB, j);
+                rc[u] = gld2(c.posC, j);
             }
             // rank of each partner's mission among the lane's partners of the round
             // (swap indices of one mission grow with the partner's mission)
@@ -1083,6 +1153,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 const int mk = q.x & 0xFFFF, rkk = (int)((uint32_t)q.x >> 16);
                 const int jk = i0 + k;
                 const TE *v = vec + k * per;
+                const TE *vx = vec + q2.z, *vy = vec + q2.w;
                 const TB *tr = trow + k * V;
                 const uint32_t *rbit = rbits + q2.y * Wm;
                 uint32_t mn = 0xFFFFFFFFu;
@@ -1090,7 +1161,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
                     for (int u = 0; u < US; ++u) {
                         const int rj = (int)((uint32_t)b[u].z >> 16);
-                        const int d = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
+                        const int d = (int)vx[a[u].y] + (int)vy[rc[u].x] + (int)v[rc[u].y]
                                     + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0);
                         const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
@@ -1103,7 +1174,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                         const int j = b0 + u * QS;
                         const int rj = (int)((uint32_t)b[u].z >> 16);
                         const int m2 = mj[u] & 0xFFFF;
-                        const int dg = (int)v[2 * Re + Ce + a[u].y] + (int)v[Re + rc[u].x] + (int)v[rc[u].y]
+                        const int dg = (int)vx[a[u].y] + (int)vy[rc[u].x] + (int)v[rc[u].y]
                                      + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
                         const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0);
@@ -1137,7 +1208,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
     const int gtid = wg * nthr + tid, gthr = nwg * nthr;
     const int M = I.M, V = I.V;
     const TE *tc = (const TE *)I.tc;
-    TB *tabu = (TB *)B.tabu;
+    TB *tabu = (TB *)B.tabu, *tabu_t = (TB *)B.tabu_t;
     const bool writer = wg == 0;
     SolveState *st = J.st;
     uint32_t nb = 0;
@@ -1160,7 +1231,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             if (tid == 0) __hip_atomic_store(&B.init_obj, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             snapshot(c0, J, tid, nthr);
         }
-        for (int k = gtid; k < M * V; k += gthr) tabu[k] = (TB)0;
+        for (int k = gtid; k < M * V; k += gthr) { tabu[k] = (TB)0; tabu_t[k] = (TB)0; }
         if (!job_barrier(B, nwg, nb, flag)) aborted = true;
         cur = __hip_atomic_load(&B.init_obj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         best = cur;
@@ -1186,8 +1257,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, tabu, smem, J.gk,
-                                         wg, nwg, t, thr, use_tabu);
+        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, tabu, tabu_t, smem,
+                                         J.gk, wg, nwg, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
         __syncthreads();
@@ -1232,6 +1303,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             if (writer && tid == 0 && use_tabu) {
                 was_tabu = (int)tabu[v * M + m] > t;
                 tabu[rs * M + m] = (TB)tval;
+                tabu_t[m * V + rs] = (TB)tval;
             }
         } else {
             const uint32_t sp = idx - c.R;
@@ -1250,6 +1322,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
                 was_tabu = (int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t;
                 tabu[r1 * M + m1] = (TB)tval;
                 tabu[r2 * M + m2] = (TB)tval;
+                tabu_t[m1 * V + r1] = (TB)tval;
+                tabu_t[m2 * V + r2] = (TB)tval;
             }
         }
         prep_next<TE>(c, global_ctx(I, B, p ^ 1, red), mv, tc, true, gtid, gthr);

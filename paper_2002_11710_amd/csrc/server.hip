@@ -239,10 +239,17 @@ struct Server {
         std::vector<InstDev> ih;
         jobs.reserve(active.size());
         for (size_t k = 0; k < active.size(); ++k) {
-            JobHost h = active[k]->job;
+            const Request *r = active[k];
+            JobHost h = r->job;
             h.inst = (int)k;
+            // a one-workgroup solve with few move slots runs proportionally more
+            // iterations per chunk (up to all that remain): small requests finish
+            // in the chunk they were admitted in instead of waiting out the large ones
+            int64_t it = chunk;
+            if (h.kind == AT_SCHED_WG) it *= std::max<int64_t>(1, kChunkSlots / std::max<int64_t>(1, h.slots));
+            h.iters = std::min<int64_t>(r->pr.max_iters - r->t, it);
             jobs.push_back(h);
-            ih.push_back(active[k]->host_inst);
+            ih.push_back(r->host_inst);
         }
         const std::vector<int> order = order_jobs(jobs);
         int rc0 = assign_groups(jobs, order);
@@ -252,14 +259,8 @@ struct Server {
             Request *r = active[(size_t)order[k]];
             int rc = fill_job(hj[k], jobs[(size_t)order[k]], r->dinst, r->scal);
             if (rc) return rc;
-            // a one-workgroup solve with few move slots runs proportionally more
-            // iterations per chunk (up to all that remain): small requests finish
-            // in the chunk they were admitted in instead of waiting out the large ones
-            const JobHost &h = jobs[(size_t)order[k]];
-            int64_t it = chunk;
-            if (h.kind == AT_SCHED_WG) it *= std::max<int64_t>(1, kChunkSlots / std::max<int64_t>(1, h.slots));
             hj[k].t_begin = r->t;
-            hj[k].t_end = (int)std::min<int64_t>(r->pr.max_iters, r->t + it);
+            hj[k].t_end = (int)(r->t + jobs[(size_t)order[k]].iters);
             hj[k].resume = 1;
             hj[k].save = 1;
             hj[k].st = r->st;
