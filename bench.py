@@ -32,9 +32,53 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 # algorithmic integer work per scored move: relocate = 2 address adds + 3 delta adds
 # + 1 min-select; swap = 4 address adds + 5 delta adds + 1 min-select
 OPS_RELOCATE, OPS_SWAP = 6, 10
-# algorithmic LDS bytes per scored move (a 16-bit gather counted as one 4-byte bank access):
-# relocate 2 travel gathers + 1 tabu read, swap 4 gathers + 2 tabu reads
-LDS_RELOCATE, LDS_SWAP = 12, 24
+# algorithmic LDS bytes per scored move in the one-workgroup (LDS-resident) kernel, a 16-bit
+# gather counted as one 4-byte bank access: relocate = 2 travel gathers, swap = 4 travel
+# gathers + the partner's tabu entry (records are wavefront broadcasts, not counted)
+LDS_RELOCATE, LDS_SWAP = 8, 20
+# LDS bandwidth: 128 bytes per clock per CU x 256 CUs x 2.4 GHz
+LDS_PEAK_BPS = 128 * 256 * 2.4e9
+COUNTERS = os.path.join(ROOT, "profiles", "counters.txt")
+
+
+def library_sha256():
+    import hashlib
+
+    import paper_2002_11710_amd._capi as capi
+    with open(capi.lib_path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def profile_counters():
+    """Per-dispatch counters of the committed rocprofv3 --pmc summary, if it was
+    taken on the library that is loaded (same sha256); else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv, kernels = {}, {}
+    with open(COUNTERS) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            w = line.split()
+            if w[0] == "kernel":
+                kernels[w[1]] = {w[i]: float(w[i + 1]) for i in range(2, len(w) - 1, 2)}
+            else:
+                kv[w[0]] = w[1]
+    if kv.get("lib_sha256") != library_sha256():
+        return None
+    kv["kernels"] = kernels
+    return kv
+
+
+def traffic_bytes(pc, kernel):
+    """HBM bytes per dispatch: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what the
+    same counters read for a plain copy of known size."""
+    if not pc or kernel not in pc["kernels"]:
+        return None
+    k = pc["kernels"][kernel]
+    return 1024.0 * (k["fetch_kib"] * float(pc["copy_fetch_factor"])
+                     + k["write_kib"] * float(pc["copy_write_factor"]))
 
 
 def move_counts(M: int, V: int):
@@ -47,15 +91,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also time an uneven batch of this many instances x 8 restarts")
-    ap.add_argument("--serve", type=str, default="",
-                    help="also run the serving stream at these arrival rates (req/s, comma separated)")
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="also time an uneven batch of this many instances x 8 restarts (0: skip)")
+    ap.add_argument("--serve", type=str, default="100,1000,5000",
+                    help="also run the serving stream at these arrival rates (req/s, comma separated; "
+                         "empty: skip)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-chunk", type=int, default=50, help="iterations per serving launch")
     ap.add_argument("--serve-slots", type=int, default=256, help="concurrent solves in the server")
-    ap.add_argument("--stress", type=int, default=0,
-                    help="also run the 256 x 10000 stress instance for this many iterations (Tabu and NS)")
+    ap.add_argument("--stress", type=int, default=1000,
+                    help="also run the 256 x 10000 stress instance for this many iterations "
+                         "(Tabu and NS; 0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-instance comparisons (profiling runs)")
@@ -93,8 +139,8 @@ def cpu_baseline(inst, budget_s=20.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(a single instance shares one device; see the sharding notes in DESIGN.md)",
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported (batches and "
+              f"serving streams would shard by solve, one share per GPU, with no exchange)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -116,6 +162,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    pc = profile_counters()
     inst = m400_instance(0)
     M, V, ITERS, TEN = inst.n_missions, inst.n_vehicles, 5000, 15
     lat = torch.tensor(inst.lat, dtype=torch.float64, device="cuda")
@@ -170,9 +217,13 @@ def main():
     evals_per_step = per_iter * (ITERS + float(np.mean(ns_iters)))
     value = evals_per_step / (ms_per_step / 1000.0)
     tabu_launch_ms = float(np.mean(tabu_ms))
-    ops = ITERS * (rel * OPS_RELOCATE + swp * OPS_SWAP)
-    achieved = ops / (tabu_launch_ms / 1000.0)
-    lds_bytes = ITERS * (rel * LDS_RELOCATE + swp * LDS_SWAP)
+    # the step's search kernel: both launches (Tabu, NS), algorithmic work over their
+    # HIP-event time, i.e. the average work per launch over the average launch duration
+    launch_ms = float(np.mean(tabu_ms) + np.mean(ns_ms))
+    it_all = ITERS + float(np.mean(ns_iters))
+    ops = it_all * (rel * OPS_RELOCATE + swp * OPS_SWAP)
+    achieved = ops / (launch_ms / 1000.0)
+    lds_bytes = it_all * (rel * LDS_RELOCATE + swp * LDS_SWAP)
     line = {
         "metric": "move evals/s (M=400 Tabu + NS step)",
         "value": value,
@@ -196,12 +247,26 @@ def main():
         "best_obj": int(rt.best_obj),
         "event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
-                     "kernel": "k_search (Tabu launch)",
-                     "lds_GBps": lds_bytes / (tabu_launch_ms / 1000.0) / 1e9},
+                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS,
+                     "traffic": traffic_bytes(pc, "k_search_multi"),
+                     "kernel": "k_search_multi (Tabu and NS launches, 64 workgroups)",
+                     "avg_launch_ms": launch_ms / 2.0,
+                     "lds_GBps": lds_bytes / (launch_ms / 1000.0) / 1e9},
     }
     if args.batch:
         line["batch"] = bench_batch(args.batch, plain=not args.no_plain)
+        b = line["batch"]
+        # the move-delta kernel at scale: LDS bytes over LDS bandwidth, with the
+        # committed counters (LDS busy time and bank-conflict stalls) when they match
+        lds = {"kernel": "k_search_wg (batch)", "achieved_GBps": b["lds_bytes_per_s"] / 1e9,
+               "peak_GBps": LDS_PEAK_BPS / 1e9, "frac": b["lds_bytes_per_s"] / LDS_PEAK_BPS,
+               "pmc_lds_busy_frac": None, "pmc_bank_conflict_frac": None, "pmc_valu_busy_frac": None,
+               "traffic": traffic_bytes(pc, "k_search_wg")}
+        if pc and "k_search_wg" in pc["kernels"]:
+            k = pc["kernels"]["k_search_wg"]
+            lds.update(pmc_lds_busy_frac=k.get("lds_busy"), pmc_bank_conflict_frac=k.get("bank_conflict"),
+                       pmc_valu_busy_frac=k.get("valu_busy"))
+        line["lds_roofline"] = lds
     if args.stress:
         line["stress"] = bench_stress(args.stress)
     if args.serve:
@@ -241,16 +306,19 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     wall = time.perf_counter() - t0
     evals = 0
     ops = 0
+    lds = 0
     for s in specs:
         rel, swp = move_counts(s["n_missions"], s["n_vehicles"])
         evals += restarts * 2000 * (rel + swp)
         ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
+        lds += restarts * 2000 * (rel * LDS_RELOCATE + swp * LDS_SWAP)
     kms = float(res[0]["search_ms"])
     assert all(r["status"] == 0 for r in res)
     out = {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
            "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
            "move_evals_per_s": evals / wall, "search_ms": kms,
-           "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS}
+           "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS,
+           "lds_bytes_per_s": lds / (kms / 1000.0)}
     if not plain:
         return out
     # the plain per-instance form: one at_solve launch per (instance, restart), in
