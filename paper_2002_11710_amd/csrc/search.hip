@@ -886,10 +886,11 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
             const int mrn = gld(o.mrow)[sn];
             adj = l + (int)gld(tc)[mrn + mc] + (int)gld(tc)[mr + y2] - a - bb - (int)gld(tc)[mrn + y2];
         }
-        gst4(n.posA, i, make_int4(mr, mc, x, y));
-        gst4(n.posB, i, make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
-                                  (int)((uint32_t)(adj + kPackBias) << 6)));
-        gst4(n.gap, i + r, make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16))));
+        // every field of a record the sweeps read is used (an unused component's
+        // register would be reused while its load is in flight, serialising the loads)
+        gst4(n.posA, i, make_int4(mc, y, a + bb, (int)((uint32_t)m | ((uint32_t)r << 16))));
+        gst4(n.posB, i, make_int4(l - a - bb, adj, 0, 0));
+        gst4(n.gap, i + r, make_int4((int)((uint32_t)x / Cs), mc, a, r));
         gst2(n.posC, i, make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs)));
         if (write_routes) {
             gst(n.seq)[i] = (uint16_t)m;
@@ -905,8 +906,7 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
         // the gap after the route's last mission
         const int e = next_off(o, mv, r + 1);
         const int x = (o0 == e) ? gld(o.vrow)[r] : gld(o.mrow)[next_seq(o, mv, e - 1)];
-        gst4(n.gap, e + r, make_int4(x, gld(o.vcol)[r], (int)gld(tc)[x + gld(o.vcol)[r]],
-                                     (int)((uint32_t)r | (((uint32_t)x / Cs) << 16))));
+        gst4(n.gap, e + r, make_int4((int)((uint32_t)x / Cs), gld(o.vcol)[r], (int)gld(tc)[x + gld(o.vcol)[r]], r));
     }
 }
 
@@ -961,10 +961,11 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         __syncthreads();   // the previous block's LDS reads are done
         for (int q = tid; q < 5 * kn; q += nthr) {
             if (q < kn) {
-                const int4 pb = gld4(c.posB, i0 + q);
-                const int r = (int)((uint32_t)pb.z >> 16);
-                mi[q] = make_int4(pb.z, pb.y - pb.x, i0 + q + r, pb.x);
-                mi2[q] = make_int4((int)((uint32_t)pb.w >> 6) - kPackBias, 0, 0, 0);
+                const int4 pa = gld4(c.posA, i0 + q);     // {pickup col, successor col, out, m | r << 16}
+                const int4 pb = gld4(c.posB, i0 + q);     // {rem, adjacent-swap delta, -, -}
+                const int r = (int)((uint32_t)pa.w >> 16);
+                mi[q] = make_int4(pa.w, pb.x, i0 + q + r, pa.z);
+                mi2[q] = make_int4(pb.y, 0, 0, 0);
             } else {
                 // the successor column (Y) and predecessor row (X) of a mission whose
                 // neighbour in the route is also in the block are that neighbour's
@@ -972,11 +973,11 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 const int e = q - kn, k = e >> 2, ty = e & 3;
                 const int4 pa = gld4(c.posA, i0 + k);
                 const int2 rc = gld2(c.posC, i0 + k);
-                const uint32_t rk = (uint32_t)gld4(c.posB, i0 + k).z >> 16;
-                const bool same_next = k + 1 < kn && ((uint32_t)gld4(c.posB, i0 + k + 1).z >> 16) == rk;
-                const bool same_prev = k > 0 && ((uint32_t)gld4(c.posB, i0 + k - 1).z >> 16) == rk;
-                const TE *src = ty == 0 ? tct + (size_t)pa.y * Rs
-                              : ty == 1 ? (same_next ? nullptr : tct + (size_t)pa.w * Rs)
+                const uint32_t rk = (uint32_t)pa.w >> 16;
+                const bool same_next = k + 1 < kn && ((uint32_t)gld4(c.posA, i0 + k + 1).w >> 16) == rk;
+                const bool same_prev = k > 0 && ((uint32_t)gld4(c.posA, i0 + k - 1).w >> 16) == rk;
+                const TE *src = ty == 0 ? tct + (size_t)pa.x * Rs
+                              : ty == 1 ? (same_next ? nullptr : tct + (size_t)pa.y * Rs)
                               : ty == 2 ? tcr + (size_t)rc.x * Cg
                                         : (same_prev ? nullptr : tcr + (size_t)rc.y * Cg);
                 tab[e] = (uint64_t)(uintptr_t)src;
@@ -999,52 +1000,67 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         __syncthreads();
         const int nd = rl[K];
-        // one pass of loads: the four travel vectors of every mission (16-byte
-        // chunks) and the missions' tabu columns (kn x V entries)
+        // the travel vectors of the block's missions in 16-byte chunks: item it < nA is
+        // chunk o of column vector v = 2k + {pickup, successor}, the rest chunk o of row
+        // vector v = 2k + {delivery, predecessor}; a null source (the vector comes from
+        // an in-block neighbour) is skipped.  Addresses are computed without branches and
+        // every thread issues all of a round's loads before its first store.  Quotients
+        // by multiply-high where exact (dividend x divisor < 2^32, divisor > 1; a
+        // divisor of 1 would need the multiplier 2^32), else by division.
         {
-            const int nA = 2 * kn * R16, nB = nA + 2 * kn * C16, nC = nB + kn * V;
-            // quotients by multiply-high where it is exact (dividend x divisor < 2^32),
-            // else by division
+            const int nA = 2 * kn * R16, nB = nA + 2 * kn * C16;
             const uint32_t mR = 0xFFFFFFFFu / (uint32_t)R16 + 1u, mC = 0xFFFFFFFFu / (uint32_t)C16 + 1u;
-            const uint32_t mV = 0xFFFFFFFFu / (uint32_t)V + 1u;
-            // (a divisor of 1 would need the multiplier 2^32: plain division there)
-            const bool fR = R16 > 1 && (uint64_t)nA * (uint64_t)R16 < (1ull << 32);
-            const bool fC = C16 > 1 && (uint64_t)(nB - nA) * (uint64_t)C16 < (1ull << 32);
-            const bool fV = V > 1 && (uint64_t)(nC - nB) * (uint64_t)V < (1ull << 32);
+            const bool fast = R16 > 1 && C16 > 1 && (uint64_t)nA * (uint64_t)R16 < (1ull << 32) &&
+                              (uint64_t)(nB - nA) * (uint64_t)C16 < (1ull << 32);
+            const uint64_t dummy = tab[0];        // the first mission's pickup column: always valid
             char *lds = (char *)vec;
-            for (int b0 = tid; b0 < nC; b0 += UL * nthr) {
-                uint4 val[UL];
-                int dst[UL], kind[UL];
+            auto stage = [&](auto quot) {
+                for (int b0 = tid; b0 < nB; b0 += UL * nthr) {
+                    uint4 val[UL];
+                    int dst[UL];
+#pragma unroll
+                    for (int u = 0; u < UL; ++u) {
+                        const int it = b0 + u * nthr;
+                        const bool inA = it < nA;
+                        const int e = inA ? it : it - nA;
+                        const int d = inA ? R16 : C16;
+                        const int v = quot(e, inA);
+                        const int o = e - v * d;
+                        const int k = v >> 1, ty = v & 1;
+                        const uint64_t sa = tab[it < nB ? 4 * k + (inA ? 0 : 2) + ty : 0];
+                        const bool ok = it < nB && sa != 0;
+                        val[u] = gld16(ok ? sa : dummy, ok ? o : 0);
+                        dst[u] = ok ? (k * per + (inA ? ty * Re : 2 * Re + ty * Ce)) * ES + 16 * o : -1;
+                    }
+#pragma unroll
+                    for (int u = 0; u < UL; ++u)
+                        if (dst[u] >= 0) *(uint4 *)(lds + dst[u]) = val[u];
+                }
+            };
+            if (fast)
+                stage([&](int e, bool inA) { return (int)__umulhi((uint32_t)e, inA ? mR : mC); });
+            else
+                stage([&](int e, bool inA) { return e / (inA ? R16 : C16); });
+        }
+        // the missions' tabu columns: kn x V entries, contiguous per mission in the
+        // mission-major copy of the table
+        {
+            const int n1 = kn * V;
+            const uint32_t mV = 0xFFFFFFFFu / (uint32_t)V + 1u;
+            const bool fast = V > 1 && (uint64_t)n1 * (uint64_t)V < (1ull << 32);
+            for (int b0 = tid; b0 < n1; b0 += UL * nthr) {
+                TB val[UL];
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
-                    const int it = b0 + u * nthr;
-                    kind[u] = it < nB ? 0 : it < nC ? 1 : 2;
-                    dst[u] = 0;
-                    val[u] = make_uint4(0u, 0u, 0u, 0u);
-                    if (it < nA) {
-                        const int v = fR ? (int)__umulhi((uint32_t)it, mR) : it / R16, o = it - v * R16;
-                        const int k = v >> 1, ty = v & 1;
-                        const uint64_t sa = tab[4 * k + ty];
-                        if (sa) val[u] = gld16(sa, o);
-                        else kind[u] = 3;
-                        dst[u] = (k * per + ty * Re) * ES + 16 * o;
-                    } else if (it < nB) {
-                        const int e = it - nA, v = fC ? (int)__umulhi((uint32_t)e, mC) : e / C16, o = e - v * C16;
-                        const int k = v >> 1, ty = v & 1;
-                        const uint64_t sa = tab[4 * k + 2 + ty];
-                        if (sa) val[u] = gld16(sa, o);
-                        else kind[u] = 3;
-                        dst[u] = (k * per + 2 * Re + ty * Ce) * ES + 16 * o;
-                    } else if (it < nC) {
-                        const int e = it - nB, k = fV ? (int)__umulhi((uint32_t)e, mV) : e / V, r = e - k * V;
-                        val[u].x = (uint32_t)gld(tabu_t)[(size_t)(mi[k].x & 0xFFFF) * V + r];
-                        dst[u] = e;
-                    }
+                    const int e = b0 + u * nthr;
+                    const int ec = e < n1 ? e : 0;
+                    const int k = fast ? (int)__umulhi((uint32_t)ec, mV) : ec / V, r = ec - k * V;
+                    val[u] = gld(tabu_t)[(size_t)(mi[k].x & 0xFFFF) * V + r];
                 }
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
-                    if (kind[u] == 0) *(uint4 *)(lds + dst[u]) = val[u];
-                    else if (kind[u] == 1) trow[dst[u]] = (TB)val[u].x;
+                    const int e = b0 + u * nthr;
+                    if (e < n1) trow[e] = val[u];
                 }
             }
         }
@@ -1091,7 +1107,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 if (!tail && (q.z + 1 < rb || q.z >= rb + UR * QR)) {
 #pragma unroll
                     for (int u = 0; u < UR; ++u) {
-                        const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
+                        const int gr = g[u].w, grow = g[u].x;
                         const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
                         const bool blk = ((int)tr[gr] > th) & !(d < thr);
                         const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
@@ -1101,7 +1117,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
                     for (int u = 0; u < UR; ++u) {
                         const int G = b0 + u * QR;
-                        const int gr = g[u].w & 0xFFFF, grow = (int)((uint32_t)g[u].w >> 16);
+                        const int gr = g[u].w, grow = g[u].x;
                         const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
                         const bool blk = ((int)tr[gr] > th) & !(d < thr);
                         const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
@@ -1125,21 +1141,20 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         for (int b0 = j0 + qs; b0 < M; b0 += US * QS) {
             const int rb = b0 - qs;
             const bool tail = rb + US * QS > M;
-            int4 a[US], b[US];
-            int2 rc[US];
+            int4 a[US];          // {pickup column, successor column, out, m | r << 16}
+            int2 rc[US];         // {delivery row, predecessor row}
             int mj[US], rk[US];
 #pragma unroll
             for (int u = 0; u < US; ++u) {
                 const int j = b0 + u * QS < M ? b0 + u * QS : j0;
                 a[u] = gld4(c.posA, j);
-                b[u] = gld4(c.posB, j);
                 rc[u] = gld2(c.posC, j);
             }
             // rank of each partner's mission among the lane's partners of the round
             // (swap indices of one mission grow with the partner's mission)
 #pragma unroll
             for (int u = 0; u < US; ++u)
-                mj[u] = b0 + u * QS < M ? (b[u].z & 0xFFFF) : 0x10000 + u;
+                mj[u] = b0 + u * QS < M ? (a[u].w & 0xFFFF) : 0x10000 + u;
 #pragma unroll
             for (int u = 0; u < US; ++u) {
                 int r = 0;
@@ -1160,9 +1175,9 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 if (!tail && rb > jk + 1) {
 #pragma unroll
                     for (int u = 0; u < US; ++u) {
-                        const int rj = (int)((uint32_t)b[u].z >> 16);
-                        const int d = (int)vx[a[u].y] + (int)vy[rc[u].x] + (int)v[rc[u].y]
-                                    + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
+                        const int rj = (int)((uint32_t)a[u].w >> 16);
+                        const int d = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
+                                    + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0);
                         const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
                                            | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
@@ -1172,10 +1187,10 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
 #pragma unroll
                     for (int u = 0; u < US; ++u) {
                         const int j = b0 + u * QS;
-                        const int rj = (int)((uint32_t)b[u].z >> 16);
+                        const int rj = (int)((uint32_t)a[u].w >> 16);
                         const int m2 = mj[u] & 0xFFFF;
-                        const int dg = (int)vx[a[u].y] + (int)vy[rc[u].x] + (int)v[rc[u].y]
-                                     + (int)v[2 * Re + a[u].w] - q.w - b[u].x;
+                        const int dg = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
+                                     + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
                         const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
                         const bool tb = ((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0);
                         const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
