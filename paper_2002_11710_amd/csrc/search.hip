@@ -173,10 +173,20 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const int y = last ? c.vcol[r] : c.mcol[c.seq[i + 1]];
         const int mc = c.mcol[m], mr = c.mrow[m];
         const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
-        // rank of m among the missions of this position's chunk
+        // rank of m among the missions of this position's chunk: the chunk's entries
+        // read 8 at a time (chunks start at multiples of 8 entries, 16-byte aligned;
+        // entries at or past M are masked)
         const int base = i - i % CH, end = min(c.M, base + CH);
         int rank = 0;
-        for (int j = base; j < end; ++j) rank += c.seq[j] < m ? 1 : 0;
+        for (int w = base; w < end; w += 8) {
+            const uint4 q = *(const uint4 *)(c.seq + w);
+            const uint32_t e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                rank += (w + 2 * h < end && (int)(e[h] & 0xFFFFu) < m) ? 1 : 0;
+                rank += (w + 2 * h + 1 < end && (int)(e[h] >> 16) < m) ? 1 : 0;
+            }
+        }
         // swapping m with its successor in the same route: P m n N -> P n m N
         int adj = 0;
         if (!last) {
