@@ -360,7 +360,9 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
 }
 
 // Deal eval units round-robin over the TW wavefronts of the solve; gw is this
-// wavefront's rank.  Returns this lane's minimum key.
+// wavefront's rank.  Units are numbered tile by tile (a tile's relocate units,
+// then its swap units); a wavefront walks the tiles once, jumping straight to
+// each of its units.  Returns this lane's minimum key.
 template <typename TE, typename TB>
 __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const TB *tabu, int gw,
                                              int TW, int lane, int t, int thr, bool use_tabu)
@@ -369,24 +371,24 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
     const int CH = c.chunk;
     const int nT = (c.M + kWave - 1) / kWave;
     const int nRC = (c.NG + CH - 1) / CH;
-    int u = 0, mine = gw;
-    for (int tl = 0; tl < nT; ++tl) {
+    int tl = 0, u = 0;   // u: number of the first unit of tile tl
+    for (int mine = gw;; mine += TW) {
+        while (tl < nT) {
+            const int nSC = (c.M - tl * kWave + CH - 1) / CH;
+            if (mine < u + nRC + nSC) break;
+            u += nRC + nSC;
+            ++tl;
+        }
+        if (tl >= nT) break;
+        const int k = mine - u;
         const int jb = tl * kWave;
-        const int nSC = (c.M - jb + CH - 1) / CH;
-        const int nu = nRC + nSC;
-        if (mine >= u + nu) { u += nu; continue; }
-        const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
-        for (int k = 0; k < nRC; ++k, ++u) {
-            if (u != mine) continue;
-            mine += TW;
+        if (k < nRC) {
+            const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
             const int G0 = k * CH, G1 = min(c.NG, G0 + CH);
             best = umin64(best, relocate_unit<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
                                                       use_tabu, rlo, rhi));
-        }
-        for (int k = 0; k < nSC; ++k, ++u) {
-            if (u != mine) continue;
-            mine += TW;
-            const int j0 = jb + k * CH, j1 = min(c.M, j0 + CH);
+        } else {
+            const int j0 = jb + (k - nRC) * CH, j1 = min(c.M, j0 + CH);
             best = umin64(best, swap_unit<TE, TB>(c, tc, tabu, tl, j0, j1, lane, t, thr, use_tabu));
         }
     }
