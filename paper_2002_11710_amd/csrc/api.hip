@@ -304,10 +304,10 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     }
     h.kind = AT_SCHED_WG;
     if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
-        // measured on gfx950 (16 x 400 missions): 512 threads, 16-column units and
+        // measured on gfx950 (16 x 400 missions): 512 threads, 8-column units and
         // about one workgroup per 3840 move slots, up to 64 workgroups
         if (!h.pr.block) h.block = 512;
-        if (!h.pr.chunk) h.chunk = 16;
+        if (!h.pr.chunk) h.chunk = 8;
         const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
         int g = h.pr.n_groups ? h.pr.n_groups
                               : (int)std::max<int64_t>(1, std::min<int64_t>(64, h.slots / 3840));
