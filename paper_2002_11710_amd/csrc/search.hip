@@ -278,9 +278,12 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
 }
 
 // ---------------------------------------------------------------------------
-// eval: swap unit (partner positions j0..j1 of one tile, j0 a chunk start)
+// eval: swap unit (partner positions j0..j1 of one tile, j0 a chunk start).
+// With units of at most 32 columns (PACK5) one 32-bit minimum per segment holds
+// the blocked bit, Δ + 2^25 and the 5-bit rank; with 64-column units the rank
+// needs 6 bits and tabu / non-tabu moves keep separate minima.
 // ---------------------------------------------------------------------------
-template <typename TE, typename TB>
+template <typename TE, typename TB, bool PACK5>
 __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const TB *tabu, int tl,
                                               int j0, int j1, int lane, int t, int thr,
                                               bool use_tabu)
@@ -293,6 +296,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     const int mri = pa.x, mci = pa.y, xri = pa.z, yci = pa.w;
     const int outb = kPackBias - pb.x;
     const int adjb = (int)((uint32_t)pb.w >> 6);   // delta of swapping with the successor, + 2^25
+    const int thrb = thr + kPackBias;              // aspiration threshold on the biased delta (thr <= 0)
     const uint32_t M = (uint32_t)c.M;
     // partners at or before the lane, or directly after it, need the masked path
     const bool diag = j0 <= tl * kWave + kWave;
@@ -310,10 +314,15 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     do {                                                                                       \
         const int d_ = outb - (b).x + (int)tc[xri + (a).y] + (int)tc[(a).x + yci]              \
                      + (int)tc[(a).z + mci] + (int)tc[mri + (a).w];                            \
-        const uint32_t p_ = ((uint32_t)d_ << 6) | ((uint32_t)(b).w & 63u);                     \
         const bool tb_ = t1 | ((int)tabu_ri[(b).z & 0xFFFF] > th);                             \
-        mT = tb_ ? min(mT, p_) : mT;                                                           \
-        mF = tb_ ? mF : min(mF, p_);                                                           \
+        if (PACK5) {                                                                           \
+            const bool bl_ = tb_ & !(d_ < thrb);                                               \
+            mF = min(mF, (bl_ ? 0x80000000u : 0u) | ((uint32_t)d_ << 5) | ((uint32_t)(b).w & 31u)); \
+        } else {                                                                               \
+            const uint32_t p_ = ((uint32_t)d_ << 6) | ((uint32_t)(b).w & 63u);                 \
+            mT = tb_ ? min(mT, p_) : mT;                                                       \
+            mF = tb_ ? mF : min(mF, p_);                                                       \
+        }                                                                                      \
     } while (0)
             for (; j + 2 <= jend; j += 2) {
                 const int4 a0 = c.posA[j], b0 = c.posB[j], a1 = c.posA[j + 1], b1 = c.posB[j + 1];
@@ -332,27 +341,43 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
                              + (int)tc[a.z + mci] + (int)tc[mri + a.w];
                 // the lane's mission directly before the partner: delta from prep
                 const int d = (j == i + 1 && ri == r) ? adjb : dg;
-                const uint32_t p = ((uint32_t)d << 6) | ((uint32_t)b.w & 63u);
                 const bool tb = t1 | ((int)tabu_ri[b.z & 0xFFFF] > th);
                 const bool ok = j > i;
-                mT = (ok && tb) ? min(mT, p) : mT;
-                mF = (ok && !tb) ? min(mF, p) : mF;
+                if (PACK5) {
+                    const bool bl = tb & !(d < thrb);
+                    const uint32_t p = (bl ? 0x80000000u : 0u) | ((uint32_t)d << 5) | ((uint32_t)b.w & 31u);
+                    mF = ok ? min(mF, p) : mF;
+                } else {
+                    const uint32_t p = ((uint32_t)d << 6) | ((uint32_t)b.w & 63u);
+                    mT = (ok && tb) ? min(mT, p) : mT;
+                    mF = (ok && !tb) ? min(mF, p) : mF;
+                }
             }
         }
         if (act) {
-            if (mF != 0xFFFFFFFFu) {
-                const int d = (int)(mF >> 6) - kPackBias;
-                const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
-                const uint32_t mj = c.seq[jw];
-                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                best = umin64(best, pack_key(false, d, swap_index(c.R, M, a, bm)));
-            }
-            if (mT != 0xFFFFFFFFu) {
-                const int d = (int)(mT >> 6) - kPackBias;
-                const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
-                const uint32_t mj = c.seq[jw];
-                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
+            if (PACK5) {
+                if (mF != 0xFFFFFFFFu) {
+                    const int d = (int)((mF >> 5) & 0x3FFFFFFu) - kPackBias;
+                    const int jw = j0 + c.prank[j0 + (int)(mF & 31u)];
+                    const uint32_t mj = c.seq[jw];
+                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                    best = umin64(best, pack_key((mF >> 31) != 0, d, swap_index(c.R, M, a, bm)));
+                }
+            } else {
+                if (mF != 0xFFFFFFFFu) {
+                    const int d = (int)(mF >> 6) - kPackBias;
+                    const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
+                    const uint32_t mj = c.seq[jw];
+                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                    best = umin64(best, pack_key(false, d, swap_index(c.R, M, a, bm)));
+                }
+                if (mT != 0xFFFFFFFFu) {
+                    const int d = (int)(mT >> 6) - kPackBias;
+                    const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
+                    const uint32_t mj = c.seq[jw];
+                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                    best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
+                }
             }
         }
     }
@@ -389,7 +414,10 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
                                                       use_tabu, rlo, rhi));
         } else {
             const int j0 = jb + (k - nRC) * CH, j1 = min(c.M, j0 + CH);
-            best = umin64(best, swap_unit<TE, TB>(c, tc, tabu, tl, j0, j1, lane, t, thr, use_tabu));
+            if (CH <= 32)
+                best = umin64(best, swap_unit<TE, TB, true>(c, tc, tabu, tl, j0, j1, lane, t, thr, use_tabu));
+            else
+                best = umin64(best, swap_unit<TE, TB, false>(c, tc, tabu, tl, j0, j1, lane, t, thr, use_tabu));
         }
     }
     return best;
