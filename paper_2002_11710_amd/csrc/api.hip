@@ -388,8 +388,9 @@ static hipStream_t class_stream(int k)
 // Launch every job of `dj` (device table in the order of `order`).  Jobs of
 // the one-workgroup schedule share one persistent launch per class (entry
 // width, tabu width, block size); the classes run concurrently on internal
-// streams.  Multi-workgroup and HBM-resident jobs get a cooperative launch
-// each, in order, on the caller's stream.
+// streams.  Then, in order on the caller's stream: one cooperative launch per
+// group of HBM-resident jobs that assign_groups put together (each job on its
+// own range of the grid), and one cooperative launch per multi-workgroup job.
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
                 Xchg *xs, hipStream_t s)
 {
@@ -470,8 +471,6 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
             k = e1;
             continue;
         }
-        if ((e = fill_u64(xs->key, kKeyNone, 3, s)) != hipSuccess) return hip_fail(e, "reset exchange");
-        if ((e = fill_u32(&xs->cnt, 0u, 5, s)) != hipSuccess) return hip_fail(e, "reset exchange");
         if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups, s)) != hipSuccess)
             return hip_fail(e, "reset exchange");
         e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);

@@ -128,14 +128,9 @@ struct JobDev {
     GlobalBufs *gb;                   // global schedule only
 };
 
-// Cross-workgroup exchange for the multi-workgroup schedules.
+// Device-side scheduling state of a call (the global schedule keeps its own in
+// each solve's GlobalBufs).
 struct Xchg {
-    uint64_t key[3];
-    uint32_t cnt;                     // grid-barrier arrivals (monotone within a launch)
-    uint32_t abort;                   // set by a workgroup whose wait ran out
-    uint32_t queue;                   // (unused slot kept for layout)
-    uint32_t pad[3];
-    int64_t init_obj;                 // greedy objective, published by workgroup 0
     // per-workgroup argmin slots of the multi-workgroup schedule, double-buffered by
     // iteration parity; bit 63 carries the iteration's tag (bit 1 of the iteration)
     uint64_t slots[2][kMaxGroups];
