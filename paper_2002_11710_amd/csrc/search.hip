@@ -588,6 +588,15 @@ __device__ __forceinline__ void snapshot(const Ctx &c, const JobDev &J, int tid,
 // ---------------------------------------------------------------------------
 // one solve, state in LDS.  MULTI: gridDim.x workgroups cooperate on job[0].
 // ---------------------------------------------------------------------------
+// The move an iteration applies, decoded by wave 0 of each workgroup
+// (LDS schedules) or by every thread (global schedule).
+struct GMove {
+    int kind;                  // 0 none, 1 relocate, 2 swap
+    int m, v, q, lo, hi, dir;  // relocate: mission, target vehicle, final position, shifted range and shift
+    int rs;                    // relocate: the mission's vehicle before the move
+    int s1, s2, m1, m2;        // swap: the two positions and their missions
+};
+
 template <typename TE, typename TB, bool MULTI>
 __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 {
@@ -600,6 +609,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
+    GMove *gm = (GMove *)(c.red + 72);   // the iteration's move, decoded by wave 0
 
     load_instance<TE>(I, c, tc, tid, nthr);
     __syncthreads();
@@ -647,6 +657,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
             w = wave_min(w);
+            uint32_t xab = 0;   // the exchange gave up waiting (uniform over the wave)
             if (MULTI) {
                 // Each workgroup publishes its minimum in its own slot, tagged with
                 // bit 1 of the iteration; wave 0 of every workgroup polls all slots
@@ -678,9 +689,59 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                     if (w2 < nwg && ready) bestk = umin64(bestk, decode_slot(v));
                 }
                 w = wave_min(bestk);
+                xab = ab;
                 if (lane == 0) c.red[65] = ab;
             }
             if (lane == 0) c.red[64] = w;
+            if (!xab && w != kKeyNone) {
+                // decode the move (uniform over the wave), publish it to the workgroup
+                // and record the tabu entries it sets (every wave is past the eval)
+                const uint32_t ix = (uint32_t)w;
+                const int tval = t + J.tenure + 1;
+                GMove mv{};
+                bool wt = false;
+                if (ix < c.R) {
+                    const int m = (int)(ix / (uint32_t)c.NG);
+                    const int G = (int)(ix - (uint32_t)m * (uint32_t)c.NG);
+                    const int v = c.gap[G].w & 0xFFFF;
+                    const int s = c.pof[m];
+                    const int rs = c.rt[s];
+                    const int fp = G - v;             // off[v] + (G - off[v] - v)
+                    const int q = fp - (fp > s ? 1 : 0);
+                    mv.kind = 1;
+                    mv.m = m; mv.v = v; mv.q = q; mv.rs = rs;
+                    mv.lo = min(s, q); mv.hi = max(s, q); mv.dir = q >= s ? 1 : -1;
+                    if (use_tabu) {
+                        wt = (int)tabu[v * M + m] > t;
+                        if (lane == 0) tabu[rs * M + m] = (TB)tval;
+                    }
+                } else {
+                    const uint32_t sp = ix - c.R;
+                    const double A = 2.0 * (double)M - 1.0;
+                    int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
+                    a = max(0, min(a, M - 2));
+                    auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
+                    while (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
+                    while (a > 0 && rowstart(a) > (int64_t)sp) --a;
+                    const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
+                    const int s1 = c.pof[m1], s2 = c.pof[m2];
+                    const int r1 = c.rt[s1], r2 = c.rt[s2];
+                    mv.kind = 2;
+                    mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
+                    mv.v = r1; mv.rs = r2;            // the two vehicles
+                    if (use_tabu) {
+                        wt = (int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t;
+                        if (lane == 0) {
+                            tabu[r1 * M + m1] = (TB)tval;
+                            tabu[r2 * M + m2] = (TB)tval;
+                        }
+                    }
+                }
+                if (lane == 0) {
+                    *gm = mv;
+                    c.red[66] = wt ? 1 : 0;
+                }
+            }
         }
         __syncthreads();
         if (MULTI && c.red[65]) { aborted = true; break; }
@@ -697,27 +758,17 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         const int d = (int)((uint32_t)(key >> 32) & 0x7FFFFFFFu) - kDeltaBias;
         const uint32_t idx = (uint32_t)key;
         if (!use_tabu && d >= 0) { stopped = 1; break; }
-        const int tval = t + J.tenure + 1;
-        bool was_tabu;
+        const bool was_tabu = c.red[66] != 0;
         const bool is_swap = idx >= c.R;
+        const GMove mv = *gm;
         if (!is_swap) {
-            const int m = (int)(idx / (uint32_t)c.NG);
-            const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
-            const int v = c.gap[G].w & 0xFFFF;
-            const int g = G - c.off[v] - v;
-            const int s = c.pof[m];
-            const int rs = c.rt[s];
-            const int fp = c.off[v] + g;
-            const int q = fp - (fp > s ? 1 : 0);
-            was_tabu = use_tabu && (int)tabu[v * M + m] > t;
-            const int lo = min(s, q), hi = max(s, q);
-            __syncthreads();
+            const int m = mv.m, v = mv.v, rs = mv.rs, q = mv.q, lo = mv.lo, hi = mv.hi;
+            const bool up = mv.dir > 0;
             int32_t *tmp = (int32_t *)c.posB;
             for (int kk = lo + tid; kk <= hi; kk += nthr)
-                tmp[kk] = (kk == q) ? m : (q >= s ? c.seq[kk + 1] : c.seq[kk - 1]);
+                tmp[kk] = (kk == q) ? m : (up ? c.seq[kk + 1] : c.seq[kk - 1]);
             if (v > rs) for (int r = rs + 1 + tid; r <= v; r += nthr) c.off[r] -= 1;
             if (v < rs) for (int r = v + 1 + tid; r <= rs; r += nthr) c.off[r] += 1;
-            if (tid == 0 && use_tabu) tabu[rs * M + m] = (TB)tval;
             __syncthreads();
             for (int kk = lo + tid; kk <= hi; kk += nthr) {
                 const int mm = tmp[kk];
@@ -728,29 +779,13 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                 c.rof[mm] = (uint16_t)r;
             }
         } else {
-            const uint32_t sp = idx - c.R;
-            const double A = 2.0 * (double)M - 1.0;
-            int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
-            a = max(0, min(a, M - 2));
-            auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
-            while (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
-            while (a > 0 && rowstart(a) > (int64_t)sp) --a;
-            const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
-            const int s1 = c.pof[m1], s2 = c.pof[m2];
-            const int r1 = c.rt[s1], r2 = c.rt[s2];
-            was_tabu = use_tabu && ((int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t);
-            __syncthreads();
             if (tid == 0) {
-                c.seq[s1] = (uint16_t)m2;
-                c.seq[s2] = (uint16_t)m1;
-                c.pof[m1] = (uint16_t)s2;
-                c.pof[m2] = (uint16_t)s1;
-                c.rof[m1] = (uint16_t)r2;
-                c.rof[m2] = (uint16_t)r1;
-                if (use_tabu) {
-                    tabu[r1 * M + m1] = (TB)tval;
-                    tabu[r2 * M + m2] = (TB)tval;
-                }
+                c.seq[mv.s1] = (uint16_t)mv.m2;
+                c.seq[mv.s2] = (uint16_t)mv.m1;
+                c.pof[mv.m1] = (uint16_t)mv.s2;
+                c.pof[mv.m2] = (uint16_t)mv.s1;
+                c.rof[mv.m1] = (uint16_t)mv.rs;
+                c.rof[mv.m2] = (uint16_t)mv.v;
             }
         }
         __syncthreads();
@@ -852,14 +887,6 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
     return c;
 }
-
-// The move an iteration applies, decoded once by every thread.
-struct GMove {
-    int kind;                  // 0 none, 1 relocate, 2 swap
-    int m, v, q, lo, hi, dir;  // relocate: mission, target vehicle, final position, shifted range and shift
-    int rs;                    // relocate: the mission's vehicle before the move
-    int s1, s2, m1, m2;        // swap: the two positions and their missions
-};
 
 // Mission, vehicle and route offsets of the routes after `mv`, read from the
 // routes before it (o): the missions between the old and new position of a
