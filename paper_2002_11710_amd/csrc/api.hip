@@ -145,9 +145,10 @@ void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
     g.tabu_t = (void *)(base + o);
     g.cur = 0;
     g.pad = 0;
-    g.key[0] = g.key[1] = g.key[2] = kKeyNone;
-    g.cnt = 0;
+    for (int b = 0; b < 2; ++b)
+        for (int w = 0; w < kMaxGroups; ++w) g.slots[b][w] = ~0ull;
     g.abort = 0;
+    g.pad2 = 0;
     g.init_obj = 0;
 }
 

@@ -101,10 +101,13 @@ struct GlobalBufs {
     void *tabu_t;                     // the same table mission-major ([mission][vehicle])
     int32_t cur;                      // which parity holds the current routes
     int32_t pad;
-    // exchange of the solve's workgroups (cleared before every launch), on its own cache lines
-    alignas(128) uint64_t key[3];     // argmin slots, by iteration mod 3
-    uint32_t cnt;                     // barrier arrivals (monotone within a launch)
+    // exchange of the solve's workgroups (reset before every launch), on their own
+    // cache lines: per-workgroup slots of each barrier (buffer b & 1 for barrier b,
+    // bit 63 = bit 1 of b, the rest an encoded key), an abort flag and the greedy
+    // objective
+    alignas(128) uint64_t slots[2][kMaxGroups];
     uint32_t abort;                   // set by a workgroup whose wait ran out
+    uint32_t pad2;
     int64_t init_obj;                 // greedy objective, published by workgroup 0
 };
 

@@ -834,30 +834,63 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 // ---------------------------------------------------------------------------
 constexpr uint64_t kBarrierTicks = 20ull * 100000000ull;   // 20 s of the 100 MHz wall clock
 
-__device__ __forceinline__ bool job_barrier(GlobalBufs &B, int nwg, uint32_t &nb, uint64_t *flag)
+// Barrier and argmin exchange of the workgroups of one HBM-resident solve.
+// Each workgroup publishes its minimum key in its own slot of the barrier's
+// buffer (barrier b uses buffer b & 1), tagged with bit 1 of b; wave 0 polls
+// every slot (one lane per slot) until all carry the tag, and the minimum of
+// all keys goes to every thread.  A workgroup is at most one barrier ahead of
+// any other, so parity buffers plus the tag never confuse barrier b with b + 2;
+// no two workgroups write one address, so arrivals do not queue on an atomic.
+// Waits are bounded by wall clock: a workgroup that runs out sets the solve's
+// abort flag, which every waiter sees.  Returns false on abort.
+__device__ __forceinline__ bool group_exchange(GlobalBufs &B, int wg, int nwg, uint32_t &nb, uint64_t key,
+                                               uint64_t *red, uint64_t &out)
 {
+    // every wavefront's global writes are complete before the slot is published
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    ++nb;
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&B.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = nb * (uint32_t)nwg;
+    const uint32_t b = nb++;
+    const uint64_t tag = (b >> 1) & 1u;
+    uint64_t *slots = B.slots[b & 1];
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        if (lane == 0)
+            __hip_atomic_store(&slots[wg], encode_slot(key, tag), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
-        uint32_t ab = 0;
-        while (__hip_atomic_load(&B.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            ab = __hip_atomic_load(&B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ab) break;
-            if (wall_clock64() - t0 > kBarrierTicks) {
-                __hip_atomic_store(&B.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ab = 1;
-                break;
+        uint64_t best = kKeyNone;
+        uint32_t ab = 0, spins = 0;
+        for (int base = 0; base < nwg && !ab; base += kWave) {
+            const int w2 = base + lane;
+            bool ready = w2 >= nwg;
+            uint64_t v = ~0ull;
+            for (;;) {
+                if (!ready) {
+                    v = __hip_atomic_load(&slots[w2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ready = (v >> 63) == tag;
+                }
+                if (__all(ready)) break;
+                if ((++spins & 63u) == 0) {
+                    ab = __hip_atomic_load(&B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (!ab && wall_clock64() - t0 > kBarrierTicks) {
+                        if (lane == 0) __hip_atomic_store(&B.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ab = 1;
+                    }
+                    if (ab) break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_s_sleep(1);
+            if (w2 < nwg && ready) best = umin64(best, decode_slot(v));
         }
+        best = wave_min(best);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *flag = ab;
+        if (lane == 0) {
+            red[66] = ab;
+            red[67] = best;
+        }
     }
     __syncthreads();
-    return *flag == 0;
+    out = red[67];
+    return red[66] == 0;
 }
 
 // Routes of parity p (p = 0, 1: double-buffered) and the records built from them.
@@ -1294,7 +1327,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
     const bool writer = wg == 0;
     SolveState *st = J.st;
     uint32_t nb = 0;
-    uint64_t *flag = red + 66;
+    uint64_t kx;
 
     int p, best_iter, stopped;
     int64_t cur, best;
@@ -1314,7 +1347,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             snapshot(c0, J, tid, nthr);
         }
         for (int k = gtid; k < M * V; k += gthr) { tabu[k] = (TB)0; tabu_t[k] = (TB)0; }
-        if (!job_barrier(B, nwg, nb, flag)) aborted = true;
+        if (!group_exchange(B, wg, nwg, nb, kKeyNone, red, kx)) aborted = true;
         cur = __hip_atomic_load(&B.init_obj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         best = cur;
         best_iter = -1;
@@ -1325,7 +1358,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
         GMove none{};
         const Ctx c = global_ctx(I, B, p, red);
         prep_next<TE>(c, c, none, tc, false, gtid, gthr);
-        if (!job_barrier(B, nwg, nb, flag)) aborted = true;
+        if (!group_exchange(B, wg, nwg, nb, kKeyNone, red, kx)) aborted = true;
     }
 
     const bool use_tabu = J.variant == AT_TABU;
@@ -1344,16 +1377,10 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
         __syncthreads();
-        if (tid < kWave) {
-            uint64_t w = lane < nwaves ? red[lane] : kKeyNone;
-            w = wave_min(w);
-            if (lane == 0) __hip_atomic_fetch_min(&B.key[t % 3], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (!job_barrier(B, nwg, nb, flag)) { aborted = true; break; }
-        const uint64_t key = __hip_atomic_load(&B.key[t % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the slot the iteration after next will use; every workgroup has read it
-        if (writer && tid == 0)
-            __hip_atomic_store(&B.key[(t + 2) % 3], kKeyNone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t wk = kKeyNone;
+        if (tid < kWave) wk = wave_min(lane < nwaves ? red[lane] : kKeyNone);
+        uint64_t key;
+        if (!group_exchange(B, wg, nwg, nb, wk, red, key)) { aborted = true; break; }
         if (key == kKeyNone) {
             if (!use_tabu) { stopped = 1; break; }
             // nothing to apply: routes and records stay as they are
@@ -1421,7 +1448,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             best_iter = t;
             pending = true;
         }
-        if (!job_barrier(B, nwg, nb, flag)) { aborted = true; break; }
+        if (!group_exchange(B, wg, nwg, nb, kKeyNone, red, kx)) { aborted = true; break; }
         p ^= 1;
     }
     if (!writer) return;
@@ -1465,17 +1492,17 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jo
     run_job_global<TE, TB>(J, b - J.g0, J.ng, smem, red);
 }
 
-// Clear the exchange state of every solve of a global-schedule launch.
+// Reset the exchange state of every solve of a global-schedule launch (one
+// workgroup per solve): every slot gets tag 1, which no first use of a buffer
+// carries, and the abort flag is cleared.
 __global__ void k_reset_global(const JobDev *jobs, int n_jobs)
 {
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n_jobs; i += (int)(gridDim.x * blockDim.x)) {
-        GlobalBufs &B = *jobs[i].gb;
-        B.key[0] = kKeyNone;
-        B.key[1] = kKeyNone;
-        B.key[2] = kKeyNone;
-        B.cnt = 0;
-        B.abort = 0;
+    GlobalBufs &B = *jobs[blockIdx.x].gb;
+    for (int w = (int)threadIdx.x; w < kMaxGroups; w += (int)blockDim.x) {
+        B.slots[0][w] = ~0ull;
+        B.slots[1][w] = ~0ull;
     }
+    if (threadIdx.x == 0) B.abort = 0;
 }
 
 // One workgroup per job; jobs are taken from an atomic queue until exhausted.
@@ -1614,7 +1641,7 @@ static hipError_t coop_launch_global(const JobDev *jobs, int n_jobs, int n_group
 hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s)
 {
-    k_reset_global<<<dim3((unsigned)((n_jobs + 255) / 256)), dim3(256), 0, s>>>(jobs, n_jobs);
+    k_reset_global<<<dim3((unsigned)n_jobs), dim3(256), 0, s>>>(jobs, n_jobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (esz16 && tb16) return coop_launch_global<uint16_t, uint16_t>(jobs, n_jobs, n_groups, block, lds_bytes, s);
