@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -528,36 +529,31 @@ int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
             int64_t want = 0;
             for (int q = a; q < b; ++q) want += jobs[(size_t)order[(size_t)q]].groups;
             if (want > cap) {
-                // water-filling by work (move slots x iterations of this launch): shares
-                // proportional to work, none above what the job asked for, at least one
-                std::vector<int64_t> w((size_t)(b - a));
-                std::vector<int> give((size_t)(b - a), 0);
-                for (int q = a; q < b; ++q) {
-                    const JobHost &h = jobs[(size_t)order[(size_t)q]];
-                    w[(size_t)(q - a)] = std::max<int64_t>(1, h.slots * std::max<int64_t>(1, h.iters));
+                // A job's launch time is about iters x (slots / groups + c): the move slots
+                // its groups share plus a per-iteration cost (apply, prep and two barriers)
+                // worth about c move slots of one workgroup, measured on gfx950.  Starting
+                // from one group each, every further group goes to the job that would
+                // finish last, up to what the job asked for; this minimises the launch's
+                // longest job, where shares proportional to work lose most to rounding
+                // when a job's share is a few groups.
+                constexpr double kIterSlots = 12288.0;
+                const int nq = b - a;
+                std::vector<int> give((size_t)nq, 1);
+                auto span = [&](int i) {
+                    const JobHost &h = jobs[(size_t)order[(size_t)(a + i)]];
+                    const double it = (double)std::max<int64_t>(1, h.iters);
+                    return it * ((double)h.slots / (double)give[(size_t)i] + kIterSlots);
+                };
+                std::priority_queue<std::pair<double, int>> pq;
+                for (int i = 0; i < nq; ++i)
+                    if (jobs[(size_t)order[(size_t)(a + i)]].groups > 1) pq.push({span(i), i});
+                for (int left = cap - nq; left > 0 && !pq.empty(); --left) {
+                    const int i = pq.top().second;
+                    pq.pop();
+                    ++give[(size_t)i];
+                    if (give[(size_t)i] < jobs[(size_t)order[(size_t)(a + i)]].groups) pq.push({span(i), i});
                 }
-                int64_t left = cap;
-                for (bool capped = true; capped;) {
-                    capped = false;
-                    double tw = 0.0;
-                    for (int q = a; q < b; ++q) if (!give[(size_t)(q - a)]) tw += (double)w[(size_t)(q - a)];
-                    for (int q = a; q < b && tw > 0.0; ++q) {
-                        if (give[(size_t)(q - a)]) continue;
-                        const int cap_q = jobs[(size_t)order[(size_t)q]].groups;
-                        if ((double)w[(size_t)(q - a)] * (double)left / tw >= (double)cap_q) {
-                            give[(size_t)(q - a)] = cap_q;
-                            left -= cap_q;
-                            capped = true;
-                            break;
-                        }
-                    }
-                }
-                double tw = 0.0;
-                for (int q = a; q < b; ++q) if (!give[(size_t)(q - a)]) tw += (double)w[(size_t)(q - a)];
-                for (int q = a; q < b; ++q)
-                    if (!give[(size_t)(q - a)])
-                        give[(size_t)(q - a)] = std::max(1, (int)((double)w[(size_t)(q - a)] * (double)left / tw));
-                for (int q = a; q < b; ++q) jobs[(size_t)order[(size_t)q]].groups = give[(size_t)(q - a)];
+                for (int i = 0; i < nq; ++i) jobs[(size_t)order[(size_t)(a + i)]].groups = give[(size_t)i];
             }
             int g0 = 0;
             for (int q = a; q < b; ++q) {

@@ -268,7 +268,8 @@ def test_batch_mixed_schedules():
 
 def test_global_shared_launch_partition():
     """More global-schedule solves than the launch can give their requested
-    workgroups: shares are cut proportionally; each result equals the solve alone."""
+    workgroups: the launch's groups are shared out (one each, then to the job that
+    would finish last); each result equals the solve alone."""
     insts = [make_instance(600 + k, 60, 4, 6, 45 + 3 * k) for k in range(12)]
     devs = [_dev(i) for i in insts]
     params = [at._capi.make_params(at.AT_TABU, 5, 40, True, 0, True, at.SCHED_GLOBAL, 64) for _ in insts]
