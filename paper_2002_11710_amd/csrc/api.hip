@@ -80,6 +80,11 @@ static int64_t tc_capacity(int L, int M, int V)
 
 int tabu_bytes(const at_params &pr) { return ((int64_t)pr.max_iters + pr.tenure + 1 <= 65535) ? 2 : 4; }
 
+int ring_slots(const at_params &pr)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)pr.tenure + 1, pr.max_iters));
+}
+
 bool may_need_global(const at_instance &in, const at_params &pr)
 {
     if (pr.schedule == AT_SCHED_GLOBAL) return true;
@@ -101,7 +106,7 @@ size_t inst_bytes(const at_instance &in, bool with_t)
 
 size_t gstate_bytes(const at_instance &in, const at_params &pr)
 {
-    return al256(sizeof(GlobalBufs)) + al256(global_state_bytes(in.n_missions, in.n_vehicles, tabu_bytes(pr)));
+    return al256(sizeof(GlobalBufs)) + al256(global_state_bytes(in.n_missions, in.n_vehicles, ring_slots(pr)));
 }
 
 void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
@@ -123,7 +128,7 @@ void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
     d.status = AT_EDEVICE;
 }
 
-void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
+void carve_gstate(GlobalBufs &g, int M, int V, int n_ring, char *base)
 {
     auto a = [](uint64_t x) { return (size_t)((x + 255u) & ~(uint64_t)255u); };
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V;
@@ -141,11 +146,9 @@ void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base)
         g.gap[k] = (int4 *)(base + o); o += a(16 * (uM + uV));
         g.posC[k] = (int2 *)(base + o); o += a(8 * uM);
     }
-    g.tabu = (void *)(base + o);
-    o += a((uint64_t)tbsz * uM * uV);
-    g.tabu_t = (void *)(base + o);
+    g.ring = (int4 *)(base + o);
+    g.ring_slots = n_ring;
     g.cur = 0;
-    g.pad = 0;
     for (int b = 0; b < 2; ++b)
         for (int w = 0; w < kMaxGroups; ++w) g.slots[b][w] = ~0ull;
     g.abort = 0;
@@ -364,7 +367,7 @@ int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> 
     for (const auto &h : jobs) {
         if (h.kind != AT_SCHED_GLOBAL) continue;
         host.emplace_back();
-        carve_gstate(host.back(), ih[(size_t)h.inst].M, ih[(size_t)h.inst].V, h.tb16 ? 2 : 4, (char *)h.gstate);
+        carve_gstate(host.back(), ih[(size_t)h.inst].M, ih[(size_t)h.inst].V, ring_slots(h.pr), (char *)h.gstate);
         hipError_t e = hipMemcpyAsync(h.gstate, &host.back(), sizeof(GlobalBufs), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "upload state tables");
     }

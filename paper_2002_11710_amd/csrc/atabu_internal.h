@@ -97,10 +97,14 @@ struct GlobalBufs {
     int32_t *off[2];
     int4 *posA[2], *posB[2], *gap[2];
     int2 *posC[2];                    // per position: exit row of its delivery, of its predecessor
-    void *tabu;                       // [vehicle][mission] expiry table
-    void *tabu_t;                     // the same table mission-major ([mission][vehicle])
+    // tabu state as a ring of the entries set in the last ring_slots iterations,
+    // two per iteration ({vehicle, mission, first iteration it is allowed again, 0};
+    // an unused entry has 0 there): every entry set earlier has expired, so a
+    // move is tabu exactly when the ring holds its (vehicle, mission) with a
+    // value above the iteration
+    int4 *ring;
+    int32_t ring_slots;               // min(tenure + 1, max_iters), at least 1
     int32_t cur;                      // which parity holds the current routes
-    int32_t pad;
     // exchange of the solve's workgroups (reset before every launch), on their own
     // cache lines: per-workgroup slots of each barrier (buffer b & 1 for barrier b,
     // bit 63 = bit 1 of b, the rest an encoded key), an abort flag and the greedy
@@ -194,12 +198,12 @@ __host__ __device__ inline int64_t compact_bound(int L, int M, int V)
 }
 
 // Bytes of the HBM state of one solve on the global schedule (GlobalBufs arrays).
-__host__ __device__ inline uint64_t global_state_bytes(int M, int V, int tbsz)
+__host__ __device__ inline uint64_t global_state_bytes(int M, int V, int ring_slots)
 {
     const uint64_t uM = (uint64_t)M, uV = (uint64_t)V, NG = uM + uV;
     auto a = [](uint64_t x) { return (x + 255u) & ~(uint64_t)255u; };
     return 8 * a(2 * uM) + 2 * a(4 * (uV + 1)) + 2 * (2 * a(16 * uM) + a(16 * NG) + a(8 * uM))
-         + 2 * a((uint64_t)tbsz * uM * uV);
+         + a(32 * (uint64_t)ring_slots);
 }
 
 __host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M + V) + M * (M - 1) / 2; }

@@ -39,11 +39,12 @@ int hip_fail(hipError_t e, const char *what);
 const char *last_error();
 int check_scalars(const at_instance *in, const at_params *pr);
 int tabu_bytes(const at_params &pr);
+int ring_slots(const at_params &pr);
 bool may_need_global(const at_instance &in, const at_params &pr);
 size_t inst_bytes(const at_instance &in, bool with_t);
 size_t gstate_bytes(const at_instance &in, const at_params &pr);
 void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t);
-void carve_gstate(GlobalBufs &g, int M, int V, int tbsz, char *base);
+void carve_gstate(GlobalBufs &g, int M, int V, int n_ring, char *base);
 int prepare_enqueue(int32_t n_inst, InstDev *dev, InstDev *host, hipStream_t s);
 int prepare_check(int32_t n_inst, const InstDev *host);
 int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s);

@@ -1028,7 +1028,7 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
 // others skip the checks.
 template <typename TE, typename TB>
 __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
-                                const TE *tcr, const TB *tabu, const TB *tabu_t, char *smem, int K,
+                                const TE *tcr, const int4 *ring, int ring_len, char *smem, int K,
                                 int wg, int nwg, int t, int thr, bool use_tabu)
 {
     constexpr int UR = 8, US = 4, UL = 8;      // relocate, swap and staging loads in flight
@@ -1059,6 +1059,12 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         const int i0 = blk * K;
         const int kn = min(K, M - i0);
         __syncthreads();   // the previous block's LDS reads are done
+        // the block's tabu state (filled from the ring once its vehicles are known):
+        // cleared here; each thread takes one ring entry along with the records
+        for (int e = tid; e < kn * Wm; e += nthr) rbits[e] = 0u;
+        if (use_tabu)
+            for (int e = tid; e < kn * V; e += nthr) trow[e] = (TB)0;
+        const int4 ren = (use_tabu && tid < ring_len) ? gld4(ring, tid) : make_int4(0, 0, 0, 0);
         for (int q = tid; q < 5 * kn; q += nthr) {
             if (q < kn) {
                 const int4 pa = gld4(c.posA, i0 + q);     // {pickup col, successor col, out, m | r << 16}
@@ -1100,6 +1106,22 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         __syncthreads();
         const int nd = rl[K];
+        // active ring entries: the vehicle column of a block mission (relocates of the
+        // mission, swaps of it into a partner's vehicle) and the mission's bit in the
+        // row of a block vehicle (swaps of a partner into that vehicle)
+        if (use_tabu) {
+            for (int e0 = 0; e0 < ring_len; e0 += nthr) {
+                const int e = e0 + tid;
+                const int4 en = e0 == 0 ? ren : (e < ring_len ? gld4(ring, e) : make_int4(0, 0, 0, 0));
+                if (e < ring_len && en.z > t) {
+                    const int r = en.x, m = en.y;
+                    for (int k = 0; k < kn; ++k)
+                        if ((mi[k].x & 0xFFFF) == m) trow[k * V + r] = (TB)en.z;
+                    for (int q = 0; q < nd; ++q)
+                        if (rl[q] == r) atomicOr(&rbits[q * Wm + (m >> 5)], 1u << (m & 31));
+                }
+            }
+        }
         // the travel vectors of the block's missions in 16-byte chunks: item it < nA is
         // chunk o of column vector v = 2k + {pickup, successor}, the rest chunk o of row
         // vector v = 2k + {delivery, predecessor}; a null source (the vector comes from
@@ -1141,52 +1163,6 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 stage([&](int e, bool inA) { return (int)__umulhi((uint32_t)e, inA ? mR : mC); });
             else
                 stage([&](int e, bool inA) { return e / (inA ? R16 : C16); });
-        }
-        // the missions' tabu columns: kn x V entries, contiguous per mission in the
-        // mission-major copy of the table
-        {
-            const int n1 = kn * V;
-            const uint32_t mV = 0xFFFFFFFFu / (uint32_t)V + 1u;
-            const bool fast = V > 1 && (uint64_t)n1 * (uint64_t)V < (1ull << 32);
-            for (int b0 = tid; b0 < n1; b0 += UL * nthr) {
-                TB val[UL];
-#pragma unroll
-                for (int u = 0; u < UL; ++u) {
-                    const int e = b0 + u * nthr;
-                    const int ec = e < n1 ? e : 0;
-                    const int k = fast ? (int)__umulhi((uint32_t)ec, mV) : ec / V, r = ec - k * V;
-                    val[u] = gld(tabu_t)[(size_t)(mi[k].x & 0xFFFF) * V + r];
-                }
-#pragma unroll
-                for (int u = 0; u < UL; ++u) {
-                    const int e = b0 + u * nthr;
-                    if (e < n1) trow[e] = val[u];
-                }
-            }
-        }
-        // the block's vehicles' tabu rows as bits: one 64-mission chunk per wave
-        {
-            const int Mc = (M + 63) >> 6, nch = nd * Mc;
-            for (int c0 = wave; c0 < nch; c0 += UL * nwaves) {
-                TB val[UL];
-#pragma unroll
-                for (int u = 0; u < UL; ++u) {
-                    const int ch = c0 + u * nwaves;
-                    const int q = ch / Mc, m = (ch - q * Mc) * 64 + lane;
-                    val[u] = (ch < nch && m < M) ? gld(tabu)[(size_t)rl[q] * M + m] : (TB)0;
-                }
-#pragma unroll
-                for (int u = 0; u < UL; ++u) {
-                    const int ch = c0 + u * nwaves;
-                    if (ch >= nch) break;   // uniform across the wave
-                    const int q = ch / Mc, cm = ch - q * Mc;
-                    const uint64_t bits = __ballot((int)val[u] > th && cm * 64 + lane < M);
-                    if (lane == 0) {
-                        rbits[q * Wm + 2 * cm] = (uint32_t)bits;
-                        if (2 * cm + 1 < Wm) rbits[q * Wm + 2 * cm + 1] = (uint32_t)(bits >> 32);
-                    }
-                }
-            }
         }
         __syncthreads();
         // relocates: every gap against the block's missions
@@ -1313,6 +1289,19 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
     return best;
 }
 
+// Whether the ring holds an active entry for (vehicle r1, mission m1) or for
+// (r2, m2) at iteration t: one wavefront, one entry per lane.
+__device__ __forceinline__ bool ring_tabu(const int4 *ring, int n, int r1, int m1, int r2, int m2, int t,
+                                          int lane)
+{
+    bool hit = false;
+    for (int e = lane; e < n; e += kWave) {
+        const int4 x = gld4(ring, e);
+        hit |= x.z > t && ((x.x == r1 && x.y == m1) || (x.x == r2 && x.y == m2));
+    }
+    return __any(hit);
+}
+
 template <typename TE, typename TB>
 __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uint64_t *red)
 {
@@ -1323,7 +1312,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
     const int gtid = wg * nthr + tid, gthr = nwg * nthr;
     const int M = I.M, V = I.V;
     const TE *tc = (const TE *)I.tc;
-    TB *tabu = (TB *)B.tabu, *tabu_t = (TB *)B.tabu_t;
+    int4 *ring = B.ring;
+    const int ring_n = B.ring_slots, ring_len = 2 * ring_n;
     const bool writer = wg == 0;
     SolveState *st = J.st;
     uint32_t nb = 0;
@@ -1346,7 +1336,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             if (tid == 0) __hip_atomic_store(&B.init_obj, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             snapshot(c0, J, tid, nthr);
         }
-        for (int k = gtid; k < M * V; k += gthr) { tabu[k] = (TB)0; tabu_t[k] = (TB)0; }
+        for (int k = gtid; k < ring_len; k += gthr) gst4(ring, k, make_int4(0, 0, 0, 0));
         if (!group_exchange(B, wg, nwg, nb, kKeyNone, red, kx)) aborted = true;
         cur = __hip_atomic_load(&B.init_obj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         best = cur;
@@ -1372,7 +1362,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, tabu, tabu_t, smem,
+        uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, ring, ring_len, smem,
                                          J.gk, wg, nwg, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
@@ -1409,10 +1399,12 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             mv.kind = 1;
             mv.m = m; mv.v = v; mv.q = q; mv.rs = rs;
             mv.lo = min(s, q); mv.hi = max(s, q); mv.dir = q >= s ? 1 : -1;
-            if (writer && tid == 0 && use_tabu) {
-                was_tabu = (int)tabu[v * M + m] > t;
-                tabu[rs * M + m] = (TB)tval;
-                tabu_t[m * V + rs] = (TB)tval;
+            if (writer && tid < kWave && use_tabu) {
+                if (J.trace) was_tabu = ring_tabu(ring, ring_len, v, m, -1, -1, t, lane);
+                if (tid == 0) {
+                    gst4(ring, 2 * (t % ring_n), make_int4(rs, m, tval, 0));
+                    gst4(ring, 2 * (t % ring_n) + 1, make_int4(0, 0, 0, 0));
+                }
             }
         } else {
             const uint32_t sp = idx - c.R;
@@ -1426,13 +1418,13 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             const int s1 = c.pof[m1], s2 = c.pof[m2];
             mv.kind = 2;
             mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
-            if (writer && tid == 0 && use_tabu) {
+            if (writer && tid < kWave && use_tabu) {
                 const int r1 = c.rt[s1], r2 = c.rt[s2];
-                was_tabu = (int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t;
-                tabu[r1 * M + m1] = (TB)tval;
-                tabu[r2 * M + m2] = (TB)tval;
-                tabu_t[m1 * V + r1] = (TB)tval;
-                tabu_t[m2 * V + r2] = (TB)tval;
+                if (J.trace) was_tabu = ring_tabu(ring, ring_len, r2, m1, r1, m2, t, lane);
+                if (tid == 0) {
+                    gst4(ring, 2 * (t % ring_n), make_int4(r1, m1, tval, 0));
+                    gst4(ring, 2 * (t % ring_n) + 1, make_int4(r2, m2, tval, 0));
+                }
             }
         }
         prep_next<TE>(c, global_ctx(I, B, p ^ 1, red), mv, tc, true, gtid, gthr);

@@ -188,7 +188,7 @@ struct Server {
                 rc[k] = plan_job(r.job, r.host_inst, false);
             }
             if (rc[k] == AT_OK && r.job.kind == AT_SCHED_GLOBAL) {
-                carve_gstate(r.gb_host, r.host_inst.M, r.host_inst.V, r.job.tb16 ? 2 : 4, (char *)r.job.gstate);
+                carve_gstate(r.gb_host, r.host_inst.M, r.host_inst.V, ring_slots(r.pr), (char *)r.job.gstate);
                 const hipError_t u = hipMemcpyAsync(r.job.gstate, &r.gb_host, sizeof(GlobalBufs),
                                                     hipMemcpyHostToDevice, s);
                 if (u != hipSuccess) rc[k] = hip_fail(u, "server: state tables");
