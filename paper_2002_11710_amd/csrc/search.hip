@@ -1031,7 +1031,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                                 const TE *tcr, const int4 *ring, int ring_len, char *smem, int K,
                                 int wg, int nwg, int t, int thr, bool use_tabu)
 {
-    constexpr int UR = 8, US = 4, UL = 8;      // relocate, swap and staging loads in flight
+    constexpr int UR = 8, US = 4;              // relocate and swap loads in flight
     constexpr int ES = (int)sizeof(TE);
     (void)tc;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -1106,6 +1106,32 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         __syncthreads();
         const int nd = rl[K];
+        // the travel vectors of the block's missions: 16-byte chunk j of the staged
+        // area belongs to mission k = j / P16, whose four vectors (pickup and successor
+        // columns, delivery and predecessor rows) follow one another.  Each wavefront
+        // loads 64 consecutive chunks straight into LDS (lane l to chunk j0 + l), so a
+        // thread's loads are all in flight at once and need no registers; a null
+        // source (the vector comes from an in-block neighbour) is skipped.  Quotients
+        // by multiply-high where exact (dividend x divisor < 2^32, divisor > 1), else
+        // by division.
+        {
+            const int P16 = 2 * R16 + 2 * C16, nch = kn * P16;
+            const uint32_t mP = 0xFFFFFFFFu / (uint32_t)P16 + 1u;
+            const bool fast = P16 > 1 && (uint64_t)nch * (uint64_t)P16 < (1ull << 32);
+            char *lds = (char *)vec;
+            for (int j0 = wave * kWave; j0 < nch; j0 += nwaves * kWave) {
+                const int j = j0 + lane;
+                const int k = fast ? (int)__umulhi((uint32_t)j, mP) : j / P16;
+                const int o = j - k * P16;
+                const int ty = o < R16 ? 0 : o < 2 * R16 ? 1 : o < 2 * R16 + C16 ? 2 : 3;
+                const int oo = o - (ty == 0 ? 0 : ty == 1 ? R16 : ty == 2 ? 2 * R16 : 2 * R16 + C16);
+                const uint64_t sa = j < nch ? tab[4 * k + ty] : 0;
+                if (sa != 0)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(uintptr_t)(sa + 16 * (uint64_t)oo),
+                        (__attribute__((address_space(3))) void *)(lds + 16 * (size_t)j0), 16, 0, 0);
+            }
+        }
         // active ring entries: the vehicle column of a block mission (relocates of the
         // mission, swaps of it into a partner's vehicle) and the mission's bit in the
         // row of a block vehicle (swaps of a partner into that vehicle)
@@ -1122,48 +1148,8 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 }
             }
         }
-        // the travel vectors of the block's missions in 16-byte chunks: item it < nA is
-        // chunk o of column vector v = 2k + {pickup, successor}, the rest chunk o of row
-        // vector v = 2k + {delivery, predecessor}; a null source (the vector comes from
-        // an in-block neighbour) is skipped.  Addresses are computed without branches and
-        // every thread issues all of a round's loads before its first store.  Quotients
-        // by multiply-high where exact (dividend x divisor < 2^32, divisor > 1; a
-        // divisor of 1 would need the multiplier 2^32), else by division.
-        {
-            const int nA = 2 * kn * R16, nB = nA + 2 * kn * C16;
-            const uint32_t mR = 0xFFFFFFFFu / (uint32_t)R16 + 1u, mC = 0xFFFFFFFFu / (uint32_t)C16 + 1u;
-            const bool fast = R16 > 1 && C16 > 1 && (uint64_t)nA * (uint64_t)R16 < (1ull << 32) &&
-                              (uint64_t)(nB - nA) * (uint64_t)C16 < (1ull << 32);
-            const uint64_t dummy = tab[0];        // the first mission's pickup column: always valid
-            char *lds = (char *)vec;
-            auto stage = [&](auto quot) {
-                for (int b0 = tid; b0 < nB; b0 += UL * nthr) {
-                    uint4 val[UL];
-                    int dst[UL];
-#pragma unroll
-                    for (int u = 0; u < UL; ++u) {
-                        const int it = b0 + u * nthr;
-                        const bool inA = it < nA;
-                        const int e = inA ? it : it - nA;
-                        const int d = inA ? R16 : C16;
-                        const int v = quot(e, inA);
-                        const int o = e - v * d;
-                        const int k = v >> 1, ty = v & 1;
-                        const uint64_t sa = tab[it < nB ? 4 * k + (inA ? 0 : 2) + ty : 0];
-                        const bool ok = it < nB && sa != 0;
-                        val[u] = gld16(ok ? sa : dummy, ok ? o : 0);
-                        dst[u] = ok ? (k * per + (inA ? ty * Re : 2 * Re + ty * Ce)) * ES + 16 * o : -1;
-                    }
-#pragma unroll
-                    for (int u = 0; u < UL; ++u)
-                        if (dst[u] >= 0) *(uint4 *)(lds + dst[u]) = val[u];
-                }
-            };
-            if (fast)
-                stage([&](int e, bool inA) { return (int)__umulhi((uint32_t)e, inA ? mR : mC); });
-            else
-                stage([&](int e, bool inA) { return e / (inA ? R16 : C16); });
-        }
+        // the staged vectors have arrived in LDS
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         // relocates: every gap against the block's missions
         for (int b0 = qr; b0 < NG; b0 += UR * QR) {
