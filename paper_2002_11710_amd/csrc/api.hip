@@ -284,6 +284,7 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
     h.block = pick_block(h.pr, h.slots);
     h.chunk = pick_chunk(h.pr, h.slots);
+    h.rchunk = h.chunk;
     h.groups = 1;
     if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit) {
         if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
@@ -309,13 +310,21 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     }
     h.kind = AT_SCHED_WG;
     if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
-        // measured on gfx950 (16 x 400 missions): 512 threads, 8-column units and
-        // about one workgroup per 3840 move slots, up to 64 workgroups
+        // measured on gfx950 (16 x 400 missions): 512 threads, 8-column swap units,
+        // relocate units twice as wide (a swap column costs about twice a relocate
+        // column, so the units take about as long), one wavefront per work unit (the
+        // iteration waits for the wavefront with the most work), up to 96 workgroups
+        // (more slots to poll cost more than the eval saves)
         if (!h.pr.block) h.block = 512;
         if (!h.pr.chunk) h.chunk = 8;
+        h.rchunk = std::min(64, 2 * h.chunk);
         const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
+        int64_t units = 0;
+        for (int64_t jb = 0; jb < d.M; jb += kWave)
+            units += (d.M + d.V + h.rchunk - 1) / h.rchunk + (d.M - jb + h.chunk - 1) / h.chunk;
+        const int64_t waves = std::max(1, h.block / kWave);
         int g = h.pr.n_groups ? h.pr.n_groups
-                              : (int)std::max<int64_t>(1, std::min<int64_t>(64, h.slots / 3840));
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(96, (units + waves - 1) / waves));
         g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
         if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
         h.kind = AT_SCHED_MULTI;
@@ -337,6 +346,7 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.t_end = h.pr.max_iters;
     j.tb16 = h.tb16;
     j.chunk = h.chunk;
+    j.rchunk = h.rchunk;
     j.seed = h.seed;
     j.out_off = h.out.route_off;
     j.out_seq = h.out.route_seq;
@@ -754,6 +764,7 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     h.out.route_seq = (int32_t *)route_seq;
     h.slots = n_slots(d.M, d.V);
     h.chunk = pick_chunk(*params, h.slots);
+    h.rchunk = h.chunk;
     h.tb16 = 0;
     h.gstate = nullptr;
     JobDev j;

@@ -121,7 +121,8 @@ struct JobDev {
     int32_t t_begin, t_end;           // iterations run by this launch
     int32_t resume, save;             // load / store `st`
     int32_t tb16;                     // tabu entries stored as uint16 in LDS
-    int32_t chunk;                    // columns per work unit
+    int32_t chunk;                    // partner positions per swap work unit
+    int32_t rchunk;                   // gaps per relocate work unit
     int32_t gk;                       // global schedule: missions staged per block
     int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
     uint64_t seed;

@@ -26,7 +26,7 @@ struct JobHost {
     int64_t slots = 0;
     int64_t iters = 0;                // iterations this launch runs (weights shared launches)
     uint32_t lds = 0;
-    int tb16 = 0, esz16 = 0, block = 256, chunk = 16, groups = 1;
+    int tb16 = 0, esz16 = 0, block = 256, chunk = 16, rchunk = 16, groups = 1;
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
     int gk = 0, gkmax = 0;            // global schedule: missions staged per block (chosen, LDS limit)
     int dM = 0, dV = 0, dR = 0, dC = 0, desz = 4;   // instance sizes (global schedule LDS plan)

@@ -45,7 +45,7 @@ struct Ctx {
     int2 *posC;     // global schedule only (row indices), else null
     uint8_t *prank;
     uint64_t *red;
-    int M, V, NG, chunk, Cs;
+    int M, V, NG, chunk, rchunk, Cs;   // chunk: swap unit width, rchunk: relocate unit width
     uint32_t R;   // relocate slots M*(M+V)
 };
 
@@ -393,9 +393,9 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
                                              int TW, int lane, int t, int thr, bool use_tabu)
 {
     uint64_t best = kKeyNone;
-    const int CH = c.chunk;
+    const int CH = c.chunk, RCH = c.rchunk;
     const int nT = (c.M + kWave - 1) / kWave;
-    const int nRC = (c.NG + CH - 1) / CH;
+    const int nRC = (c.NG + RCH - 1) / RCH;
     int tl = 0, u = 0;   // u: number of the first unit of tile tl
     for (int mine = gw;; mine += TW) {
         while (tl < nT) {
@@ -409,7 +409,7 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
         const int jb = tl * kWave;
         if (k < nRC) {
             const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
-            const int G0 = k * CH, G1 = min(c.NG, G0 + CH);
+            const int G0 = k * RCH, G1 = min(c.NG, G0 + RCH);
             best = umin64(best, relocate_unit<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
                                                       use_tabu, rlo, rhi));
         } else {
@@ -462,7 +462,7 @@ __device__ void dump_keys(const Ctx &c, const TE *tc, const int32_t *tabu, int t
 // ---------------------------------------------------------------------------
 // LDS setup
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V, int chunk, int Cs)
+__device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V, int chunk, int rchunk, int Cs)
 {
     Ctx c;
     c.mrow = (int32_t *)(smem + ly.mrow);
@@ -484,6 +484,7 @@ __device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V,
     c.V = V;
     c.NG = M + V;
     c.chunk = chunk;
+    c.rchunk = rchunk;
     c.Cs = Cs;
     c.R = (uint32_t)M * (uint32_t)(M + V);
     return c;
@@ -605,7 +606,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), (int)sizeof(TB));
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, I.Cs);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, I.Cs);
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
@@ -916,6 +917,7 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.V = I.V;
     c.NG = I.M + I.V;
     c.chunk = 0;
+    c.rchunk = 0;
     c.Cs = I.Cs;
     c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
     return c;
@@ -1523,7 +1525,7 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), 4);
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, I.Cs);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, I.Cs);
     TE *tc = (TE *)(smem + ly.tc);
     int32_t *tabu = (int32_t *)(smem + ly.tabu);
     load_instance<TE>(I, c, tc, tid, nthr);
