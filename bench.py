@@ -249,7 +249,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS,
                      "traffic": traffic_bytes(pc, "k_search_multi"),
-                     "kernel": "k_search_multi (Tabu and NS launches, 64 workgroups)",
+                     "kernel": "k_search_multi (the Tabu and the NS launch of the step)",
                      "avg_launch_ms": launch_ms / 2.0,
                      "lds_GBps": lds_bytes / (launch_ms / 1000.0) / 1e9},
     }

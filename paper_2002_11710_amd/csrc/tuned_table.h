@@ -9,10 +9,10 @@ namespace at {
 struct TunedRow { int64_t max_slots; int block; int chunk; };
 static const TunedRow kTuned[] = {
     {4000, 256, 8},
-    {12000, 256, 16},
+    {12000, 256, 32},
     {30000, 256, 32},
-    {60000, 512, 16},
+    {60000, 512, 32},
     {100000, 1024, 32},
-    {INT64_MAX, 1024, 16},
+    {INT64_MAX, 1024, 32},
 };
 }  // namespace at
