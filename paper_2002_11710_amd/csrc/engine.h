@@ -16,6 +16,7 @@ namespace at {
 constexpr uint32_t kLdsLimit = 160u * 1024u - 64u;
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t al16c(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // One solve as the host plans it.
 struct JobHost {

@@ -30,6 +30,30 @@ namespace {
 // of iterations per launch.
 constexpr int64_t kChunkSlots = 1 << 18;
 
+// Requests whose small records (saved-state table, prepared instance, HBM state
+// table) one scatter round places; larger admission batches take several rounds.
+constexpr int kScatterBatch = 256;
+
+// One record of an admission batch: `bytes` (a multiple of 4) at `off` in the
+// staging buffer go to `dst`.
+struct Scatter {
+    char *dst;
+    uint32_t off, bytes;
+};
+
+// Copy each staged record to its place: one workgroup per record.
+__global__ void k_scatter(const Scatter *e, const char *stage)
+{
+    const Scatter x = e[blockIdx.x];
+    const uint32_t *src = (const uint32_t *)(stage + x.off);
+    uint32_t *dst = (uint32_t *)x.dst;
+    for (uint32_t i = threadIdx.x; i < x.bytes / 4; i += blockDim.x) dst[i] = src[i];
+}
+
+constexpr size_t kStageRecord = al16c(sizeof(SolveState)) + al16c(sizeof(InstDev)) + al16c(sizeof(GlobalBufs));
+static_assert(sizeof(SolveState) % 4 == 0 && sizeof(InstDev) % 4 == 0 && sizeof(GlobalBufs) % 4 == 0,
+              "scattered records are copied in 4-byte words");
+
 struct Arena {
     char *base = nullptr;
     size_t size = 0;
@@ -120,12 +144,20 @@ struct Server {
     std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
     std::vector<JobDev> table;        // host copy of the last launch's job table
+    // admission: prepared-instance table, and the staging of the records one
+    // scatter launch places (device, and pinned host memory)
+    InstDev *dprep = nullptr;
+    std::vector<InstDev> hprep;
+    char *dstage = nullptr, *hstage = nullptr;
+    Scatter *dscat = nullptr, *hscat = nullptr;
 
     ~Server()
     {
         if (in_flight && done_ev) (void)hipEventSynchronize(done_ev);
         for (auto &kv : all) delete kv.second;
         if (done_ev) (void)hipEventDestroy(done_ev);
+        if (hstage) (void)hipHostFree(hstage);
+        if (hscat) (void)hipHostFree(hscat);
         if (dev) (void)hipFree(dev);
     }
 
@@ -157,29 +189,37 @@ struct Server {
         return st;
     }
 
-    // Admit a batch of requests whose arena blocks are allocated: upload their
-    // state tables, prepare every instance (one stream synchronisation for the
-    // batch), plan their solves.  A request that fails is finished with its
+    // Admit a batch of requests whose arena blocks are allocated: prepare every
+    // instance in one set of launches (one stream synchronisation for the batch),
+    // plan their solves, and place their state tables and prepared instances with
+    // one copy and one scatter launch.  A request that fails is finished with its
     // error status and its memory released; the others are returned in `ok`.
     void admit_batch(const std::vector<Request *> &batch, std::vector<Request *> &ok)
     {
-        std::vector<int> rc(batch.size(), AT_OK);
-        for (size_t k = 0; k < batch.size(); ++k) {
+        const size_t n = batch.size();
+        std::vector<int> rc(n, AT_OK);
+        hprep.resize(n);
+        for (size_t k = 0; k < n; ++k) {
             Request &r = *batch[k];
             r.slot = free_slots.back();
             free_slots.pop_back();
             r.scal = dscal + r.slot;
             // state table: pointers, valid = 0 (the first chunk starts from the greedy solution)
             r.st_host = carve(r);
-            hipError_t e = hipMemcpyAsync(r.st, &r.st_host, sizeof(SolveState), hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) { rc[k] = hip_fail(e, "server: state upload"); continue; }
-            rc[k] = prepare_enqueue(1, r.dinst, &r.host_inst, s);
+            hprep[k] = r.host_inst;
         }
-        hipError_t e = hipStreamSynchronize(s);
-        for (size_t k = 0; k < batch.size(); ++k) {
+        // every instance of the batch in one set of prepare launches
+        const int prc = prepare_enqueue((int32_t)n, dprep, hprep.data(), s);
+        hipError_t e = prc == AT_OK ? hipStreamSynchronize(s) : hipSuccess;
+        std::vector<Request *> cand;
+        for (size_t k = 0; k < n; ++k) {
             Request &r = *batch[k];
-            if (rc[k] == AT_OK && e != hipSuccess) rc[k] = hip_fail(e, "server: prepare");
-            if (rc[k] == AT_OK) rc[k] = prepare_check(1, &r.host_inst);
+            if (prc) rc[k] = prc;
+            else if (e != hipSuccess) rc[k] = hip_fail(e, "server: prepare");
+            if (rc[k] == AT_OK) {
+                r.host_inst = hprep[k];
+                rc[k] = prepare_check(1, &r.host_inst);
+            }
             if (rc[k] == AT_OK) {
                 r.job.inst = 0;
                 r.job.pr = r.pr;
@@ -187,25 +227,64 @@ struct Server {
                 r.job.seed = r.pr.restart_seed;
                 rc[k] = plan_job(r.job, r.host_inst, false);
             }
-            if (rc[k] == AT_OK && r.job.kind == AT_SCHED_GLOBAL) {
+            if (rc[k] == AT_OK && r.job.kind == AT_SCHED_GLOBAL)
                 carve_gstate(r.gb_host, r.host_inst.M, r.host_inst.V, ring_slots(r.pr), (char *)r.job.gstate);
-                const hipError_t u = hipMemcpyAsync(r.job.gstate, &r.gb_host, sizeof(GlobalBufs),
-                                                    hipMemcpyHostToDevice, s);
-                if (u != hipSuccess) rc[k] = hip_fail(u, "server: state tables");
-            }
             if (rc[k] != AT_OK) {
-                r.done = true;
-                r.last.status = rc[k];
-                arena.release(r.mem, r.bytes);
-                r.mem = nullptr;
-                free_slots.push_back(r.slot);
-                r.slot = -1;
+                finish_failed(r, rc[k]);
                 continue;
             }
-            r.admitted = true;
-            r.t = 0;
-            ok.push_back(&r);
+            cand.push_back(&r);
         }
+        // their records (saved-state table, prepared instance, HBM state table) placed
+        // by one copy and one scatter launch per round of kScatterBatch requests
+        int src = AT_OK;
+        for (size_t a = 0; a < cand.size() && src == AT_OK; a += kScatterBatch) {
+            const size_t b = std::min(cand.size(), a + kScatterBatch);
+            if (a > 0 && (e = hipStreamSynchronize(s)) != hipSuccess) {   // the staging is reused
+                src = hip_fail(e, "server: admission");
+                break;
+            }
+            uint32_t off = 0, ne = 0;
+            auto put = [&](void *dst, const void *rec, size_t bytes) {
+                std::memcpy(hstage + off, rec, bytes);
+                hscat[ne++] = Scatter{(char *)dst, off, (uint32_t)bytes};
+                off += (uint32_t)al16c(bytes);
+            };
+            for (size_t q = a; q < b; ++q) {
+                Request &r = *cand[q];
+                put(r.st, &r.st_host, sizeof(SolveState));
+                put(r.dinst, &r.host_inst, sizeof(InstDev));
+                if (r.job.kind == AT_SCHED_GLOBAL) put(r.job.gstate, &r.gb_host, sizeof(GlobalBufs));
+            }
+            if ((e = hipMemcpyAsync(dstage, hstage, off, hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(dscat, hscat, sizeof(Scatter) * ne, hipMemcpyHostToDevice, s)) != hipSuccess) {
+                src = hip_fail(e, "server: admission upload");
+                break;
+            }
+            k_scatter<<<dim3(ne), dim3(256), 0, s>>>(dscat, dstage);
+            if ((e = hipGetLastError()) != hipSuccess) src = hip_fail(e, "server: admission scatter");
+        }
+        for (Request *r : cand) {
+            if (src != AT_OK) {
+                finish_failed(*r, src);
+                continue;
+            }
+            r->admitted = true;
+            r->t = 0;
+            ok.push_back(r);
+        }
+    }
+
+    // A request that could not be admitted: finished with its error status, its
+    // memory and slot released.
+    void finish_failed(Request &r, int status)
+    {
+        r.done = true;
+        r.last.status = status;
+        arena.release(r.mem, r.bytes);
+        r.mem = nullptr;
+        free_slots.push_back(r.slot);
+        r.slot = -1;
     }
 
     // Retire finished solves after the last launch completed.
@@ -290,8 +369,10 @@ int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_i
     if (!server) return fail(AT_EINVAL, "null server handle");
     if (max_slots < 1 || max_slots > 65536) return fail(AT_EINVAL, "max_slots outside [1, 65536]");
     if (chunk_iters < 1) return fail(AT_EINVAL, "chunk_iters must be positive");
+    const size_t nstage = (size_t)std::min(max_slots, kScatterBatch);
     const size_t fixed = al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots)
-                       + al256(sizeof(JobScal) * (size_t)max_slots);
+                       + al256(sizeof(JobScal) * (size_t)max_slots) + al256(sizeof(InstDev) * (size_t)max_slots)
+                       + al256(kStageRecord * nstage) + al256(3 * sizeof(Scatter) * nstage);
     if (hbm_budget_bytes < fixed + (1 << 20)) return fail(AT_ENOMEM, "budget too small");
     Server *sv = new Server();
     sv->s = (hipStream_t)stream;
@@ -302,7 +383,19 @@ int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_i
     if (e != hipSuccess) { delete sv; return hip_fail(e, "server arena"); }
     sv->xs = (Xchg *)sv->dev;
     sv->djobs = (JobDev *)(sv->dev + al256(sizeof(Xchg)));
-    sv->dscal = (JobScal *)(sv->dev + al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots));
+    size_t o = al256(sizeof(Xchg)) + al256(sizeof(JobDev) * (size_t)max_slots);
+    sv->dscal = (JobScal *)(sv->dev + o);
+    o += al256(sizeof(JobScal) * (size_t)max_slots);
+    sv->dprep = (InstDev *)(sv->dev + o);
+    o += al256(sizeof(InstDev) * (size_t)max_slots);
+    sv->dstage = sv->dev + o;
+    o += al256(kStageRecord * nstage);
+    sv->dscat = (Scatter *)(sv->dev + o);
+    if ((e = hipHostMalloc((void **)&sv->hstage, kStageRecord * nstage, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&sv->hscat, 3 * sizeof(Scatter) * nstage, hipHostMallocDefault)) != hipSuccess) {
+        delete sv;
+        return hip_fail(e, "server staging");
+    }
     sv->hscal.assign((size_t)max_slots, JobScal{});
     for (int k = max_slots - 1; k >= 0; --k) sv->free_slots.push_back(k);
     sv->arena.init(sv->dev + fixed, hbm_budget_bytes - fixed);
