@@ -240,6 +240,20 @@ def test_global_schedule_short_routes(groups):
         assert_same_result(o, g, f"global 24x40 variant {variant} groups {groups}")
 
 
+@pytest.mark.parametrize("tenure,iters", [(0, 60), (1, 60), (40, 30), (300, 400)])
+def test_global_schedule_tenure_edges(tenure, iters):
+    """The HBM-resident schedule keeps its tabu state as a ring of the entries of
+    the last min(tenure + 1, iterations) iterations: no tenure, tenure 1, a
+    tenure beyond the budget (the ring never wraps) and a ring longer than a
+    workgroup's threads give the oracle's trajectories, tabu flags included."""
+    inst = make_instance(91, 40, 3, 4, 36)
+    for variant in (at.AT_TABU, at.AT_NS):
+        _, o = oracle_solve(inst, variant=variant, tenure=tenure, iters=iters)
+        g = at.solve(_dev(inst), variant=variant, tenure=tenure, iters=iters,
+                     schedule=at.SCHED_GLOBAL, n_groups=4)
+        assert_same_result(o, g, f"global tenure {tenure} iters {iters} variant {variant}")
+
+
 def test_stress_instance_prefix():
     """The 256-vehicle x 10000-mission instance: greedy start and the first
     iterations against the oracle (each oracle iteration scores 1.5e8 moves)."""

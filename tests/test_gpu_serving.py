@@ -144,3 +144,21 @@ def test_mix_with_hbm_resident_requests():
         srv.close()
     _, o = oracle_solve(big[0], tenure=9, iters=60)
     assert_same_result(o, alone[0], "large request alone vs oracle")
+
+
+def test_admission_batch_over_one_scatter_round():
+    """300 requests admitted at once: more than one round of the admission
+    scatter (256 requests) places their records.  Every request finishes, a
+    sample equals the solve alone and two equal the oracle."""
+    insts = [make_instance(900 + k, 12, 2, 2, 8 + k % 7) for k in range(300)]
+    devs = [_dev(i) for i in insts]
+    srv = at.Server(1 << 30, max_slots=320, chunk_iters=20)
+    tickets = [srv.submit(d, tenure=3, iters=20, trace=True) for d in devs]
+    got = _drive(srv, list(tickets))
+    srv.close()
+    for k in range(0, 300, 10):
+        alone = at.solve(devs[k], tenure=3, iters=20, trace=True)
+        _same(alone, got[tickets[k]], f"request {k} of 300")
+    for k in (0, 299):
+        _, o = oracle_solve(insts[k], tenure=3, iters=20)
+        assert_same_result(o, got[tickets[k]], f"request {k} of 300 vs oracle")
