@@ -238,7 +238,7 @@ __host__ __device__ inline int staged_cols(int C, int esz) { const int q = 16 / 
 // records and a vehicle slot per mission, and the vehicle count.
 __host__ __device__ inline uint32_t global_table_bytes(int K)
 {
-    return (uint32_t)(32 * K + 32 * K + ((4 * K + 4 + 15) & ~15));
+    return (uint32_t)(32 * K + 32 * K + ((4 * K + 8 + 15) & ~15));
 }
 
 // LDS bytes of the global schedule's mission-major eval: the per-block tables,

@@ -29,6 +29,8 @@
 // index order for a fixed lane: the gap offset for relocates, the partner's
 // mission id for swaps (ranked inside the chunk by prep), so ties resolve to
 // the smallest slot index exactly as the full 64-bit comparison would.
+#include <type_traits>
+
 #include "atabu_internal.h"
 #include "atabu.h"
 
@@ -1046,7 +1048,8 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
     uint64_t *tab = (uint64_t *)smem;             // source pointers, 4 per mission
     int4 *mi = (int4 *)(tab + 4 * K);             // {m | r << 16, rem, own gap, out}
     int4 *mi2 = mi + K;                           // {adjacent-swap delta, vehicle slot, -, -}
-    int *rl = (int *)(mi2 + K);                   // the block's vehicles; their count at rl[K]
+    int *rl = (int *)(mi2 + K);                   // the block's vehicles; their count at rl[K],
+                                                  // at rl[K + 1] whether any tabu entry is active for them
     TE *vec = (TE *)(smem + global_table_bytes(K));
     TB *trow = (TB *)((char *)vec + (((size_t)K * per * sizeof(TE) + 15) & ~(size_t)15));
     uint32_t *rbits = (uint32_t *)((char *)trow + (((size_t)K * V * sizeof(TB) + 15) & ~(size_t)15));
@@ -1064,6 +1067,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         // the block's tabu state (filled from the ring once its vehicles are known):
         // cleared here; each thread takes one ring entry along with the records
         for (int e = tid; e < kn * Wm; e += nthr) rbits[e] = 0u;
+        if (tid == 0) rl[K + 1] = 0;
         if (use_tabu)
             for (int e = tid; e < kn * V; e += nthr) trow[e] = (TB)0;
         const int4 ren = (use_tabu && tid < ring_len) ? gld4(ring, tid) : make_int4(0, 0, 0, 0);
@@ -1143,136 +1147,145 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
                 const int4 en = e0 == 0 ? ren : (e < ring_len ? gld4(ring, e) : make_int4(0, 0, 0, 0));
                 if (e < ring_len && en.z > t) {
                     const int r = en.x, m = en.y;
+                    bool hit = false;
                     for (int k = 0; k < kn; ++k)
-                        if ((mi[k].x & 0xFFFF) == m) trow[k * V + r] = (TB)en.z;
+                        if ((mi[k].x & 0xFFFF) == m) { trow[k * V + r] = (TB)en.z; hit = true; }
                     for (int q = 0; q < nd; ++q)
-                        if (rl[q] == r) atomicOr(&rbits[q * Wm + (m >> 5)], 1u << (m & 31));
+                        if (rl[q] == r) { atomicOr(&rbits[q * Wm + (m >> 5)], 1u << (m & 31)); hit = true; }
+                    if (hit) rl[K + 1] = 1;
                 }
             }
         }
         // the staged vectors have arrived in LDS
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        // relocates: every gap against the block's missions
-        for (int b0 = qr; b0 < NG; b0 += UR * QR) {
-            const int rb = b0 - qr;                       // first column of the round
-            const bool tail = rb + UR * QR > NG;
-            int4 g[UR];
+        // the sweeps, with the tabu lookups only where an active entry concerns the
+        // block (otherwise no move of the block is tabu)
+        auto sweeps = [&](auto tab_on) {
+            constexpr bool TAB = decltype(tab_on)::value;
+            // relocates: every gap against the block's missions
+            for (int b0 = qr; b0 < NG; b0 += UR * QR) {
+                const int rb = b0 - qr;                       // first column of the round
+                const bool tail = rb + UR * QR > NG;
+                int4 g[UR];
 #pragma unroll
-            for (int u = 0; u < UR; ++u) {
-                const int G = b0 + u * QR;
-                g[u] = gld4(c.gap, G < NG ? G : 0);
-            }
-            for (int k = pr; k < kn; k += PR) {
-                const int4 q = mi[k];
-                const TE *v = vec + k * per;
-                const TB *tr = trow + k * V;
-                uint32_t mn = 0xFFFFFFFFu;
-                if (!tail && (q.z + 1 < rb || q.z >= rb + UR * QR)) {
-#pragma unroll
-                    for (int u = 0; u < UR; ++u) {
-                        const int gr = g[u].w, grow = g[u].x;
-                        const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
-                        const bool blk = ((int)tr[gr] > th) & !(d < thr);
-                        const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
-                        mn = min(mn, key);
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < UR; ++u) {
-                        const int G = b0 + u * QR;
-                        const int gr = g[u].w, grow = g[u].x;
-                        const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
-                        const bool blk = ((int)tr[gr] > th) & !(d < thr);
-                        const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
-                        const bool skip = (G >= NG) | ((unsigned)(G - q.z) < 2u);
-                        mn = skip ? mn : min(mn, key);
-                    }
+                for (int u = 0; u < UR; ++u) {
+                    const int G = b0 + u * QR;
+                    g[u] = gld4(c.gap, G < NG ? G : 0);
                 }
-                if (mn != 0xFFFFFFFFu) {
-                    const int G = b0 + (int)(mn & 31u) * QR;
-                    const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
-                    best = umin64(best, pack_key((mn >> 31) != 0, d,
-                                                 (uint32_t)(q.x & 0xFFFF) * (uint32_t)NG + (uint32_t)G));
-                }
-            }
-        }
-        // swaps: every later position against the block's missions
-        const int j0 = i0 + 1;
-        int QS = kWave;
-        while (QS < nthr && QS * US < M - j0) QS <<= 1;
-        const int PS = nthr / QS, ps = tid / QS, qs = tid - ps * QS;
-        for (int b0 = j0 + qs; b0 < M; b0 += US * QS) {
-            const int rb = b0 - qs;
-            const bool tail = rb + US * QS > M;
-            int4 a[US];          // {pickup column, successor column, out, m | r << 16}
-            int2 rc[US];         // {delivery row, predecessor row}
-            int mj[US], rk[US];
+                for (int k = pr; k < kn; k += PR) {
+                    const int4 q = mi[k];
+                    const TE *v = vec + k * per;
+                    const TB *tr = trow + k * V;
+                    uint32_t mn = 0xFFFFFFFFu;
+                    if (!tail && (q.z + 1 < rb || q.z >= rb + UR * QR)) {
 #pragma unroll
-            for (int u = 0; u < US; ++u) {
-                const int j = b0 + u * QS < M ? b0 + u * QS : j0;
-                a[u] = gld4(c.posA, j);
-                rc[u] = gld2(c.posC, j);
-            }
-            // rank of each partner's mission among the lane's partners of the round
-            // (swap indices of one mission grow with the partner's mission)
+                        for (int u = 0; u < UR; ++u) {
+                            const int gr = g[u].w, grow = g[u].x;
+                            const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
+                            const bool blk = (TAB && (int)tr[gr] > th) & !(d < thr);
+                            const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
+                            mn = min(mn, key);
+                        }
+                    } else {
 #pragma unroll
-            for (int u = 0; u < US; ++u)
-                mj[u] = b0 + u * QS < M ? (a[u].w & 0xFFFF) : 0x10000 + u;
-#pragma unroll
-            for (int u = 0; u < US; ++u) {
-                int r = 0;
-#pragma unroll
-                for (int w = 0; w < US; ++w) r += (w != u && mj[w] < mj[u]) ? 1 : 0;
-                rk[u] = r;
-            }
-            for (int k = ps; k < kn; k += PS) {
-                const int4 q = mi[k];
-                const int4 q2 = mi2[k];
-                const int mk = q.x & 0xFFFF, rkk = (int)((uint32_t)q.x >> 16);
-                const int jk = i0 + k;
-                const TE *v = vec + k * per;
-                const TE *vx = vec + q2.z, *vy = vec + q2.w;
-                const TB *tr = trow + k * V;
-                const uint32_t *rbit = rbits + q2.y * Wm;
-                uint32_t mn = 0xFFFFFFFFu;
-                if (!tail && rb > jk + 1) {
-#pragma unroll
-                    for (int u = 0; u < US; ++u) {
-                        const int rj = (int)((uint32_t)a[u].w >> 16);
-                        const int d = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
-                                    + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
-                        const bool tb = ((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0);
-                        const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
-                                           | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
-                        mn = min(mn, key);
+                        for (int u = 0; u < UR; ++u) {
+                            const int G = b0 + u * QR;
+                            const int gr = g[u].w, grow = g[u].x;
+                            const int d = q.y + (int)v[grow] + (int)v[2 * Re + g[u].y] - g[u].z;
+                            const bool blk = (TAB && (int)tr[gr] > th) & !(d < thr);
+                            const uint32_t key = (blk ? 0x80000000u : 0u) | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)u;
+                            const bool skip = (G >= NG) | ((unsigned)(G - q.z) < 2u);
+                            mn = skip ? mn : min(mn, key);
+                        }
                     }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < US; ++u) {
-                        const int j = b0 + u * QS;
-                        const int rj = (int)((uint32_t)a[u].w >> 16);
-                        const int m2 = mj[u] & 0xFFFF;
-                        const int dg = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
-                                     + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
-                        const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
-                        const bool tb = ((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0);
-                        const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
-                                           | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
-                        mn = ((j >= M) | (j <= jk)) ? mn : min(mn, key);
+                    if (mn != 0xFFFFFFFFu) {
+                        const int G = b0 + (int)(mn & 31u) * QR;
+                        const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
+                        best = umin64(best, pack_key((mn >> 31) != 0, d,
+                                                     (uint32_t)(q.x & 0xFFFF) * (uint32_t)NG + (uint32_t)G));
                     }
                 }
-                if (mn != 0xFFFFFFFFu) {
-                    const int r = (int)(mn & 31u);
-                    int mw = mj[0];
+            }
+            // swaps: every later position against the block's missions
+            const int j0 = i0 + 1;
+            int QS = kWave;
+            while (QS < nthr && QS * US < M - j0) QS <<= 1;
+            const int PS = nthr / QS, ps = tid / QS, qs = tid - ps * QS;
+            for (int b0 = j0 + qs; b0 < M; b0 += US * QS) {
+                const int rb = b0 - qs;
+                const bool tail = rb + US * QS > M;
+                int4 a[US];          // {pickup column, successor column, out, m | r << 16}
+                int2 rc[US];         // {delivery row, predecessor row}
+                int mj[US], rk[US];
 #pragma unroll
-                    for (int u = 1; u < US; ++u) mw = rk[u] == r ? mj[u] : mw;
-                    const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
-                    const uint32_t lo = (uint32_t)min(mk, mw), hi = (uint32_t)max(mk, mw);
-                    best = umin64(best, pack_key((mn >> 31) != 0, d, swap_index(c.R, (uint32_t)M, lo, hi)));
+                for (int u = 0; u < US; ++u) {
+                    const int j = b0 + u * QS < M ? b0 + u * QS : j0;
+                    a[u] = gld4(c.posA, j);
+                    rc[u] = gld2(c.posC, j);
+                }
+                // rank of each partner's mission among the lane's partners of the round
+                // (swap indices of one mission grow with the partner's mission)
+#pragma unroll
+                for (int u = 0; u < US; ++u)
+                    mj[u] = b0 + u * QS < M ? (a[u].w & 0xFFFF) : 0x10000 + u;
+#pragma unroll
+                for (int u = 0; u < US; ++u) {
+                    int r = 0;
+#pragma unroll
+                    for (int w = 0; w < US; ++w) r += (w != u && mj[w] < mj[u]) ? 1 : 0;
+                    rk[u] = r;
+                }
+                for (int k = ps; k < kn; k += PS) {
+                    const int4 q = mi[k];
+                    const int4 q2 = mi2[k];
+                    const int mk = q.x & 0xFFFF, rkk = (int)((uint32_t)q.x >> 16);
+                    const int jk = i0 + k;
+                    const TE *v = vec + k * per;
+                    const TE *vx = vec + q2.z, *vy = vec + q2.w;
+                    const TB *tr = trow + k * V;
+                    const uint32_t *rbit = rbits + q2.y * Wm;
+                    uint32_t mn = 0xFFFFFFFFu;
+                    if (!tail && rb > jk + 1) {
+#pragma unroll
+                        for (int u = 0; u < US; ++u) {
+                            const int rj = (int)((uint32_t)a[u].w >> 16);
+                            const int d = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
+                                        + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
+                            const bool tb = TAB && (((int)tr[rj] > th) | (((rbit[mj[u] >> 5] >> (mj[u] & 31)) & 1u) != 0));
+                            const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
+                                               | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
+                            mn = min(mn, key);
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < US; ++u) {
+                            const int j = b0 + u * QS;
+                            const int rj = (int)((uint32_t)a[u].w >> 16);
+                            const int m2 = mj[u] & 0xFFFF;
+                            const int dg = (int)vx[a[u].x] + (int)vy[rc[u].x] + (int)v[rc[u].y]
+                                         + (int)v[2 * Re + a[u].y] - q.w - a[u].z;
+                            const int d = (j == jk + 1 && rkk == rj) ? q2.x : dg;
+                            const bool tb = TAB && (((int)tr[rj] > th) | (((rbit[m2 >> 5] >> (m2 & 31)) & 1u) != 0));
+                            const uint32_t key = ((tb & !(d < thr)) ? 0x80000000u : 0u)
+                                               | ((uint32_t)(d + kPackBias) << 5) | (uint32_t)rk[u];
+                            mn = ((j >= M) | (j <= jk)) ? mn : min(mn, key);
+                        }
+                    }
+                    if (mn != 0xFFFFFFFFu) {
+                        const int r = (int)(mn & 31u);
+                        int mw = mj[0];
+#pragma unroll
+                        for (int u = 1; u < US; ++u) mw = rk[u] == r ? mj[u] : mw;
+                        const int d = (int)((mn >> 5) & 0x3FFFFFFu) - kPackBias;
+                        const uint32_t lo = (uint32_t)min(mk, mw), hi = (uint32_t)max(mk, mw);
+                        best = umin64(best, pack_key((mn >> 31) != 0, d, swap_index(c.R, (uint32_t)M, lo, hi)));
+                    }
                 }
             }
-        }
+        };
+        if (rl[K + 1]) sweeps(std::true_type{});
+        else sweeps(std::false_type{});
     }
     return best;
 }
