@@ -147,7 +147,7 @@ struct Xchg {
 
 struct Lay {
     uint32_t tc, mrow, mcol, vrow, vcol, off, seq, rt, rof, pof;
-    uint32_t posA, posB, gap, prank, tabu, red, total;
+    uint32_t posA, posB, gap, gend, prank, tabu, red, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
@@ -171,6 +171,7 @@ __host__ __device__ inline Lay lds_layout(int M, int V, int R, int Cs, int esz, 
     AT_TAKE(posA, 16 * uM);
     AT_TAKE(posB, 16 * uM);
     AT_TAKE(gap, 16 * NG);
+    AT_TAKE(gend, 2 * NG);
     AT_TAKE(prank, uM);
     AT_TAKE(tabu, (uint64_t)tbsz * uM * uV);
     AT_TAKE(red, 1024);

@@ -44,6 +44,7 @@ struct Ctx {
     int32_t *mrow, *mcol, *vrow, *vcol, *off;
     uint16_t *seq, *rt, *rof, *pof;
     int4 *posA, *posB, *gap;
+    uint16_t *gend;  // per gap: the first gap of the next route (LDS schedules only)
     int2 *posC;     // global schedule only (row indices), else null
     uint8_t *prank;
     uint64_t *red;
@@ -202,6 +203,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         c.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
                               (int)((uint32_t)rank | ((uint32_t)(adj + kPackBias) << 6)));
         c.gap[i + r] = make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        c.gend[i + r] = (uint16_t)(c.off[r + 1] + r + 1);
         if (c.posC) c.posC[i] = make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs));
     }
     for (int r = tid; r < c.V; r += nthr) {
@@ -209,6 +211,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
         c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]],
                                  (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        c.gend[e + r] = (uint16_t)(e + r + 1);
     }
 }
 
@@ -232,8 +235,9 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
     uint64_t best = kKeyNone;
     int G = G0;
     while (G < G1) {
+        // the segment's vehicle and end: two independent loads
         const int r = c.gap[G].w & 0xFFFF;
-        const int Gend = min(G1, c.off[r + 1] + r + 1);
+        const int Gend = min(G1, (int)c.gend[G]);
         const bool tb = use_tabu && (int)tabu[r * c.M + m] > t;
         uint32_t pm = 0xFFFFFFFFu;
         // four columns per step: all their LDS reads are in flight together
@@ -479,6 +483,7 @@ __device__ __forceinline__ Ctx make_ctx(char *smem, const Lay &ly, int M, int V,
     c.posA = (int4 *)(smem + ly.posA);
     c.posB = (int4 *)(smem + ly.posB);
     c.gap = (int4 *)(smem + ly.gap);
+    c.gend = (uint16_t *)(smem + ly.gend);
     c.prank = (uint8_t *)(smem + ly.prank);
     c.posC = nullptr;
     c.red = (uint64_t *)(smem + ly.red);
@@ -912,6 +917,7 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.posA = B.posA[p];
     c.posB = B.posB[p];
     c.gap = B.gap[p];
+    c.gend = nullptr;
     c.posC = B.posC[p];
     c.prank = nullptr;
     c.red = red;
