@@ -147,10 +147,10 @@ void carve_gstate(GlobalBufs &g, int M, int V, int n_ring, char *base)
         g.posC[k] = (int2 *)(base + o); o += a(8 * uM);
     }
     g.ring = (int4 *)(base + o);
+    o += a(32 * (uint64_t)n_ring);
+    g.slots = (uint64_t *)(base + o);   // set by the reset before every launch
     g.ring_slots = n_ring;
     g.cur = 0;
-    for (int b = 0; b < 2; ++b)
-        for (int w = 0; w < kMaxGroups; ++w) g.slots[b][w] = ~0ull;
     g.abort = 0;
     g.pad2 = 0;
     g.init_obj = 0;
@@ -487,7 +487,7 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
             k = e1;
             continue;
         }
-        if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups, s)) != hipSuccess)
+        if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups * kSlotStride, s)) != hipSuccess)
             return hip_fail(e, "reset exchange");
         e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
         if (e != hipSuccess) return hip_fail(e, "cooperative search launch");

@@ -676,7 +676,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                 const uint64_t tag = (uint64_t)((rel >> 1) & 1);
                 uint64_t *slots = xs->slots[rel & 1];
                 if (lane == 0)
-                    __hip_atomic_store(&slots[wg], encode_slot(w, tag), __ATOMIC_RELAXED,
+                    __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 uint64_t bestk = kKeyNone;
                 uint32_t ab = 0;
@@ -687,7 +687,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                     uint32_t spins = 0;
                     for (;;) {
                         if (!ready) {
-                            v = __hip_atomic_load(&slots[w2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            v = __hip_atomic_load(&slots[w2 * kSlotStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             ready = (v >> 63) == tag;
                         }
                         if (__all(ready)) break;
@@ -859,11 +859,12 @@ __device__ __forceinline__ bool group_exchange(GlobalBufs &B, int wg, int nwg, u
     __syncthreads();
     const uint32_t b = nb++;
     const uint64_t tag = (b >> 1) & 1u;
-    uint64_t *slots = B.slots[b & 1];
+    uint64_t *slots = B.slots + (size_t)(b & 1) * kMaxGroups * kSlotStride;
     if (threadIdx.x < kWave) {
         const int lane = threadIdx.x;
         if (lane == 0)
-            __hip_atomic_store(&slots[wg], encode_slot(key, tag), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(key, tag), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
         uint64_t best = kKeyNone;
         uint32_t ab = 0, spins = 0;
@@ -873,7 +874,7 @@ __device__ __forceinline__ bool group_exchange(GlobalBufs &B, int wg, int nwg, u
             uint64_t v = ~0ull;
             for (;;) {
                 if (!ready) {
-                    v = __hip_atomic_load(&slots[w2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    v = __hip_atomic_load(&slots[w2 * kSlotStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ready = (v >> 63) == tag;
                 }
                 if (__all(ready)) break;
@@ -1497,10 +1498,7 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jo
 __global__ void k_reset_global(const JobDev *jobs, int n_jobs)
 {
     GlobalBufs &B = *jobs[blockIdx.x].gb;
-    for (int w = (int)threadIdx.x; w < kMaxGroups; w += (int)blockDim.x) {
-        B.slots[0][w] = ~0ull;
-        B.slots[1][w] = ~0ull;
-    }
+    for (int w = (int)threadIdx.x; w < 2 * kMaxGroups; w += (int)blockDim.x) B.slots[w * kSlotStride] = ~0ull;
     if (threadIdx.x == 0) B.abort = 0;
 }
 
