@@ -218,6 +218,65 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
 // ---------------------------------------------------------------------------
 // eval: relocate unit (columns G0..G1 of one tile)
 // ---------------------------------------------------------------------------
+// Relocate unit of the multi-workgroup schedule, 16-bit travel entries
+// (|delta| < 2^19): the tabu entries of the unit's vehicles (gaps are
+// route-ordered, so a unit of at most 64 gaps spans at most 64 vehicles) are
+// gathered up front into a 64-bit mask per lane, then one 32-bit minimum of
+// blocked << 31 | (delta + 2^24) << 6 | column rank runs over all the unit's
+// columns with no per-route step, so a unit over many short routes takes no
+// longer than another (the iteration waits for the slowest wavefront).  For a
+// fixed lane the slot index grows with the rank: ties resolve as the 64-bit keys
+// would.
+constexpr int32_t kFlatBias = 1 << 24;
+
+template <typename TE, typename TB>
+__device__ __forceinline__ uint64_t relocate_unit_flat(const Ctx &c, const TE *tc, const TB *tabu,
+                                                       int tl, int G0, int G1, int lane, int t, int thr,
+                                                       bool use_tabu)
+{
+    const int i = tl * kWave + lane;
+    const bool act = i < c.M;
+    const int ii = act ? i : tl * kWave;
+    const int4 pa = c.posA[ii], pb = c.posB[ii];
+    const int m = pb.z & 0xFFFF, ri = (int)((uint32_t)pb.z >> 16);
+    const int mr = pa.x, mc = pa.y;
+    const int remb = pb.y - pb.x + kFlatBias;
+    const int thrb = thr < -kFlatBias ? 0 : thr + kFlatBias;   // d >= thr on the biased delta
+    const int Gi = ii + ri;
+    const int r0 = c.gap[G0].w & 0xFFFF, r1 = c.gap[G1 - 1].w & 0xFFFF;
+    uint64_t tmask = 0;
+    if (use_tabu) {
+#pragma unroll 4
+        for (int r = r0; r <= r1; ++r)
+            tmask |= (uint64_t)((int)tabu[r * c.M + m] > t ? 1u : 0u) << (r - r0);
+    }
+    uint32_t pm = 0xFFFFFFFFu;
+#define AT_RELOC_FLAT(gv, Gv)                                                                  \
+    do {                                                                                       \
+        const int db_ = remb + (int)tc[(gv).x + mc] + (int)tc[mr + (gv).y] - (gv).z;           \
+        const uint32_t bl_ = (uint32_t)(tmask >> (((gv).w & 0xFFFF) - r0)) & (db_ >= thrb ? 1u : 0u); \
+        const uint32_t k_ = (bl_ << 31) | ((uint32_t)db_ << 6) | (uint32_t)((Gv) - G0);        \
+        pm = ((unsigned)((Gv) - Gi) >= 2u) ? min(pm, k_) : pm;                                 \
+    } while (0)
+    int G = G0;
+    for (; G + 4 <= G1; G += 4) {
+        const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+        AT_RELOC_FLAT(g0, G);
+        AT_RELOC_FLAT(g1, G + 1);
+        AT_RELOC_FLAT(g2, G + 2);
+        AT_RELOC_FLAT(g3, G + 3);
+    }
+    for (; G < G1; ++G) {
+        const int4 g0 = c.gap[G];
+        AT_RELOC_FLAT(g0, G);
+    }
+#undef AT_RELOC_FLAT
+    if (!act || pm == 0xFFFFFFFFu) return kKeyNone;
+    const int d = (int)((pm >> 6) & 0x1FFFFFFu) - kFlatBias;
+    const uint32_t Gw = (uint32_t)G0 + (pm & 63u);
+    return pack_key((pm >> 31) != 0, d, (uint32_t)m * (uint32_t)c.NG + Gw);
+}
+
 template <typename TE, typename TB>
 __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, const TB *tabu,
                                                   int tl, int G0, int G1, int lane, int t, int thr,
@@ -394,7 +453,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
 // wavefront's rank.  Units are numbered tile by tile (a tile's relocate units,
 // then its swap units); a wavefront walks the tiles once, jumping straight to
 // each of its units.  Returns this lane's minimum key.
-template <typename TE, typename TB>
+template <typename TE, typename TB, bool FLAT = false>
 __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const TB *tabu, int gw,
                                              int TW, int lane, int t, int thr, bool use_tabu)
 {
@@ -416,8 +475,12 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
         if (k < nRC) {
             const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
             const int G0 = k * RCH, G1 = min(c.NG, G0 + RCH);
-            best = umin64(best, relocate_unit<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
-                                                      use_tabu, rlo, rhi));
+            if constexpr (FLAT && sizeof(TE) == 2)
+                best = umin64(best, relocate_unit_flat<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
+                                                               use_tabu));
+            else
+                best = umin64(best, relocate_unit<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
+                                                          use_tabu, rlo, rhi));
         } else {
             const int j0 = jb + (k - nRC) * CH, j1 = min(c.M, j0 + CH);
             if (CH <= 32)
@@ -658,7 +721,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_all<TE, TB>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
+        uint64_t k = eval_all<TE, TB, MULTI>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) c.red[wave] = k;
         __syncthreads();
