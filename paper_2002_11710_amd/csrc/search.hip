@@ -453,16 +453,35 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
 // wavefront's rank.  Units are numbered tile by tile (a tile's relocate units,
 // then its swap units); a wavefront walks the tiles once, jumping straight to
 // each of its units.  Returns this lane's minimum key.
+// Where a wavefront's units begin: the tile of unit gw and the number of that
+// tile's first unit, and the solve's unit count (fixed for a solve, so computed
+// once instead of walking the tiles every iteration).
+struct UnitStart { int tl, u, n; };
+
+__device__ __forceinline__ UnitStart unit_start(const Ctx &c, int gw)
+{
+    const int nT = (c.M + kWave - 1) / kWave;
+    const int nRC = (c.NG + c.rchunk - 1) / c.rchunk;
+    UnitStart s{nT, 0, 0};
+    for (int tl = 0; tl < nT; ++tl) {
+        const int nU = nRC + (c.M - tl * kWave + c.chunk - 1) / c.chunk;
+        if (s.tl == nT && gw < s.n + nU) { s.tl = tl; s.u = s.n; }
+        s.n += nU;
+    }
+    return s;
+}
+
 template <typename TE, typename TB, bool FLAT = false>
 __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const TB *tabu, int gw,
-                                             int TW, int lane, int t, int thr, bool use_tabu)
+                                             int TW, const UnitStart &us, int lane, int t, int thr,
+                                             bool use_tabu)
 {
     uint64_t best = kKeyNone;
     const int CH = c.chunk, RCH = c.rchunk;
     const int nT = (c.M + kWave - 1) / kWave;
     const int nRC = (c.NG + RCH - 1) / RCH;
-    int tl = 0, u = 0;   // u: number of the first unit of tile tl
-    for (int mine = gw;; mine += TW) {
+    int tl = us.tl, u = us.u;   // u: number of the first unit of tile tl
+    for (int mine = gw; mine < us.n; mine += TW) {
         while (tl < nT) {
             const int nSC = (c.M - tl * kWave + CH - 1) / CH;
             if (mine < u + nRC + nSC) break;
@@ -711,6 +730,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 
     const bool use_tabu = J.variant == AT_TABU;
     const int gw = wg * nwaves + wave, TW = nwaves * nwg;
+    const UnitStart us0 = unit_start(c, gw);
     int t = J.t_begin;
     bool aborted = false;
     for (; t < J.t_end && !stopped; ++t) {
@@ -721,7 +741,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
             const int64_t g = best - cur;
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
-        uint64_t k = eval_all<TE, TB, MULTI>(c, tc, tabu, gw, TW, lane, t, thr, use_tabu);
+        uint64_t k = eval_all<TE, TB, MULTI>(c, tc, tabu, gw, TW, us0, lane, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) c.red[wave] = k;
         __syncthreads();
@@ -1628,7 +1648,7 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     }
     const bool use_tabu = J.variant == AT_TABU;
     dump_keys<TE>(c, tc, tabu, tid, nthr, t, thr, use_tabu, keys);
-    uint64_t k = eval_all<TE, int32_t>(c, tc, tabu, wave, nwaves, lane, t, thr, use_tabu);
+    uint64_t k = eval_all<TE, int32_t>(c, tc, tabu, wave, nwaves, unit_start(c, wave), lane, t, thr, use_tabu);
     k = wave_min(k);
     if (lane == 0) c.red[wave] = k;
     __syncthreads();
