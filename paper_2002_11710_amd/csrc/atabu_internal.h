@@ -34,6 +34,7 @@
 //             G = off[v+1] + v the gap before vehicle v's return; ga = exit row
 //             offset on its left, gb = entry column on its right, gc = T[ga][gb],
 //             gr = its vehicle
+//   gend[G] = first gap of the next vehicle's route (where G's route ends)
 //   prank[c*chunk + k] = position (within chunk c) of the mission of rank k
 #pragma once
 

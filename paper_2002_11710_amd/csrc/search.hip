@@ -168,7 +168,6 @@ template <typename TE>
 __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nthr)
 {
     const int CH = c.chunk;
-    const uint32_t Cs = (uint32_t)c.Cs;
     for (int i = tid; i < c.M; i += nthr) {
         const int m = c.seq[i], r = c.rt[i];
         const int x = (i == c.off[r]) ? c.vrow[r] : c.mrow[c.seq[i - 1]];
@@ -179,7 +178,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         // rank of m among the missions of this position's chunk: the chunk's entries
         // read 8 at a time (chunks start at multiples of 8 entries, 16-byte aligned;
         // entries at or past M are masked)
-        const int base = i - i % CH, end = min(c.M, base + CH);
+        const int base = i & ~(CH - 1), end = min(c.M, base + CH);   // CH: a power of two
         int rank = 0;
         for (int w = base; w < end; w += 8) {
             const uint4 q = *(const uint4 *)(c.seq + w);
@@ -202,15 +201,13 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         c.posA[i] = make_int4(mr, mc, x, y);
         c.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
                               (int)((uint32_t)rank | ((uint32_t)(adj + kPackBias) << 6)));
-        c.gap[i + r] = make_int4(x, mc, a, (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        c.gap[i + r] = make_int4(x, mc, a, r);
         c.gend[i + r] = (uint16_t)(c.off[r + 1] + r + 1);
-        if (c.posC) c.posC[i] = make_int2((int)((uint32_t)mr / Cs), (int)((uint32_t)x / Cs));
     }
     for (int r = tid; r < c.V; r += nthr) {
         const int e = c.off[r + 1];
         const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
-        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]],
-                                 (int)((uint32_t)r | (((uint32_t)x / Cs) << 16)));
+        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]], r);
         c.gend[e + r] = (uint16_t)(e + r + 1);
     }
 }
@@ -480,10 +477,11 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
     const int CH = c.chunk, RCH = c.rchunk;
     const int nT = (c.M + kWave - 1) / kWave;
     const int nRC = (c.NG + RCH - 1) / RCH;
+    const int lgCH = __builtin_ctz((unsigned)CH);   // CH: a power of two
     int tl = us.tl, u = us.u;   // u: number of the first unit of tile tl
     for (int mine = gw; mine < us.n; mine += TW) {
         while (tl < nT) {
-            const int nSC = (c.M - tl * kWave + CH - 1) / CH;
+            const int nSC = (c.M - tl * kWave + CH - 1) >> lgCH;
             if (mine < u + nRC + nSC) break;
             u += nRC + nSC;
             ++tl;
