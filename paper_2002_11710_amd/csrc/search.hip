@@ -204,7 +204,9 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         c.gap[i + r] = make_int4(x, mc, a, r);
         c.gend[i + r] = (uint16_t)(c.off[r + 1] + r + 1);
     }
-    for (int r = tid; r < c.V; r += nthr) {
+    // the gaps after each route's last mission: on the highest threads, which have
+    // no position of their own when M < nthr, so no thread runs two record chains
+    for (int r = nthr - 1 - tid; r < c.V; r += nthr) {
         const int e = c.off[r + 1];
         const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
         c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]], r);
@@ -853,15 +855,18 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (!is_swap) {
             const int m = mv.m, v = mv.v, rs = mv.rs, q = mv.q, lo = mv.lo, hi = mv.hi;
             const bool up = mv.dir > 0;
+            // each position between the old and the new place takes the mission (and
+            // vehicle: only the moved mission changes vehicle) of its neighbour
             int32_t *tmp = (int32_t *)c.posB;
-            for (int kk = lo + tid; kk <= hi; kk += nthr)
-                tmp[kk] = (kk == q) ? m : (up ? c.seq[kk + 1] : c.seq[kk - 1]);
+            for (int kk = lo + tid; kk <= hi; kk += nthr) {
+                const int src = up ? kk + 1 : kk - 1;
+                tmp[kk] = (kk == q) ? (m | (v << 16)) : ((int)c.seq[src] | ((int)c.rt[src] << 16));
+            }
             if (v > rs) for (int r = rs + 1 + tid; r <= v; r += nthr) c.off[r] -= 1;
             if (v < rs) for (int r = v + 1 + tid; r <= rs; r += nthr) c.off[r] += 1;
             __syncthreads();
             for (int kk = lo + tid; kk <= hi; kk += nthr) {
-                const int mm = tmp[kk];
-                const int r = route_of_pos(c.off, V, kk);
+                const int mm = tmp[kk] & 0xFFFF, r = (int)((uint32_t)tmp[kk] >> 16);
                 c.seq[kk] = (uint16_t)mm;
                 c.rt[kk] = (uint16_t)r;
                 c.pof[mm] = (uint16_t)kk;
