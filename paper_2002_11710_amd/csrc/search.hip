@@ -796,7 +796,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                     const int G = (int)(ix - (uint32_t)m * (uint32_t)c.NG);
                     const int v = c.gap[G].w & 0xFFFF;
                     const int s = c.pof[m];
-                    const int rs = c.rt[s];
+                    const int rs = c.rof[m];          // loads alongside pof[m]
                     const int fp = G - v;             // off[v] + (G - off[v] - v)
                     const int q = fp - (fp > s ? 1 : 0);
                     mv.kind = 1;
@@ -816,7 +816,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                     while (a > 0 && rowstart(a) > (int64_t)sp) --a;
                     const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
                     const int s1 = c.pof[m1], s2 = c.pof[m2];
-                    const int r1 = c.rt[s1], r2 = c.rt[s2];
+                    const int r1 = c.rof[m1], r2 = c.rof[m2];
                     mv.kind = 2;
                     mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
                     mv.v = r1; mv.rs = r2;            // the two vehicles
@@ -1484,11 +1484,12 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
         if (!is_swap) {
             const int m = (int)(idx / (uint32_t)c.NG);
             const int G = (int)(idx - (uint32_t)m * (uint32_t)c.NG);
+            // the gap's vehicle and the mission's position and vehicle: three
+            // independent loads (the insertion point off[v] + g is G - v)
             const int v = c.gap[G].w & 0xFFFF;
-            const int g = G - c.off[v] - v;
             const int s = c.pof[m];
-            const int rs = c.rt[s];
-            const int fp = c.off[v] + g;
+            const int rs = c.rof[m];
+            const int fp = G - v;
             const int q = fp - (fp > s ? 1 : 0);
             mv.kind = 1;
             mv.m = m; mv.v = v; mv.q = q; mv.rs = rs;
@@ -1513,7 +1514,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             mv.kind = 2;
             mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
             if (writer && tid < kWave && use_tabu) {
-                const int r1 = c.rt[s1], r2 = c.rt[s2];
+                const int r1 = c.rof[m1], r2 = c.rof[m2];
                 if (J.trace) was_tabu = ring_tabu(ring, ring_len, r2, m1, r1, m2, t, lane);
                 if (tid == 0) {
                     gst4(ring, 2 * (t % ring_n), make_int4(r1, m1, tval, 0));
