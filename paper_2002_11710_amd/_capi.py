@@ -283,7 +283,7 @@ class Server:
                  stream=None):
         L = lib()
         if not hasattr(L, "at_server_create"):
-            raise AtError(AT_EINVAL, "this build has no server")
+            raise AtError(AT_EINVAL, "the loaded library has no server entry points")
         self._h = C.c_void_p()
         self._pending = {}
         _check(L.at_server_create(int(hbm_budget_bytes), int(max_slots), int(chunk_iters),
