@@ -71,6 +71,41 @@ def test_every_slot_key(shape, chunk):
                 assert fast == int(want.min()), (shape, k, t, best - cur, hex(fast), hex(int(want.min())))
 
 
+@pytest.mark.parametrize("chunk", [8, 32])
+def test_every_slot_key_wide_entries(chunk):
+    """Travel times above 65535 s (5 km/h): the compact block holds 32-bit
+    entries, and every slot's key and the minimum still equal the oracle's."""
+    inst = make_instance(211, 60, 4, 7, 130)
+    P = oracle.Problem.from_instance(inst, speed_kmh=5.0)
+    assert int(P.T.max()) > 65535
+    dev = at.DeviceInstance.from_instance(inst, speed_kmh=5.0)
+    rng = np.random.default_rng(5)
+    states = [(*P.greedy(0), np.full((P.M, P.V), -1, np.int32)), _random_state(P, rng)]
+    for k, (off, seq, tabu) in enumerate(states):
+        cur = P.objective(off, seq)
+        for best in (cur, cur - 5000):
+            want = P.keys(off, seq, tabu, 6, cur, best)
+            got, fast = at.debug_eval_moves(dev, off, seq, tabu, 6, cur, best, chunk=chunk)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, (k, best - cur, bad[:5])
+            assert fast == int(want.min()), (k, best - cur)
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 0), (2, 7), (3, 4)])
+def test_wide_entries_trajectory(sched, groups):
+    """32-bit travel entries (5 km/h) under the one-workgroup, multi-workgroup
+    (its relocate units then keep per-route segments) and HBM-resident
+    schedules: Tabu and NS trajectories equal the oracle's."""
+    inst = make_instance(212, 200, 5, 6, 150)
+    P = oracle.Problem.from_instance(inst, speed_kmh=5.0)
+    assert int(P.T.max()) > 65535
+    dev = at.DeviceInstance.from_instance(inst, speed_kmh=5.0)
+    for variant in (at.AT_TABU, at.AT_NS):
+        o = P.solve(variant=variant, tenure=9, iters=300)
+        g = at.solve(dev, variant=variant, tenure=9, iters=300, schedule=sched, n_groups=groups)
+        assert_same_result(o, g, f"wide entries schedule {sched} groups {groups} variant {variant}")
+
+
 # ------------------------------------------------------------------ whole trajectories
 
 def test_small_workload_tabu_trajectory():
