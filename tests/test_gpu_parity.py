@@ -202,6 +202,19 @@ def test_edge_cases():
     assert_same_result(o, g, "no aspiration")
 
 
+@pytest.mark.parametrize("sched,groups", [(2, 0), (2, 5), (3, 3)])
+def test_cooperative_schedules_tenure_and_aspiration(sched, groups):
+    """The multi-workgroup and HBM-resident schedules with tenure 0, a short
+    tenure without aspiration and a longer one, on 40 vehicles for 120 missions
+    (many empty routes, so relocate units span many vehicles)."""
+    inst = make_instance(213, 90, 8, 40, 120)
+    dev = _dev(inst)
+    for tenure, asp in ((0, 1), (3, 0), (12, 1)):
+        _, o = oracle_solve(inst, tenure=tenure, iters=200, aspiration=asp)
+        g = at.solve(dev, tenure=tenure, iters=200, aspiration=bool(asp), schedule=sched, n_groups=groups)
+        assert_same_result(o, g, f"schedule {sched} groups {groups} tenure {tenure} aspiration {asp}")
+
+
 def test_bad_device_inputs_are_rejected():
     inst = small_instance(0)
     dev = _dev(inst)
