@@ -230,6 +230,7 @@ hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, in
 int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
 // Missions staged per block by the global schedule's eval, at most.
 constexpr int kGlobalKMax = 64;
+static_assert(kGlobalKMax <= kWave, "a block's missions fit one wavefront");
 // Threads per workgroup of the global schedule, at most.
 constexpr int kGlobalBlock = 512;
 

@@ -1189,19 +1189,26 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
             }
         }
         __syncthreads();
-        for (int q = tid; q < kn; q += nthr) {
-            // the block's vehicles in order (positions are route-ordered) and each mission's slot
-            const int r = (int)((uint32_t)mi[q].x >> 16);
-            int slot = 0;
-            for (int k = 1; k <= q; ++k) slot += ((uint32_t)mi[k].x >> 16) != ((uint32_t)mi[k - 1].x >> 16) ? 1 : 0;
-            mi2[q].y = slot;
-            if (q == 0 || ((uint32_t)mi[q - 1].x >> 16) != (uint32_t)r) rl[slot] = r;
-            if (q == kn - 1) rl[K] = slot + 1;
-            // where the mission's predecessor row and successor column sit in LDS
-            const bool same_prev = q > 0 && ((uint32_t)mi[q - 1].x >> 16) == (uint32_t)r;
-            const bool same_next = q + 1 < kn && ((uint32_t)mi[q + 1].x >> 16) == (uint32_t)r;
-            mi2[q].z = same_prev ? (q - 1) * per + 2 * Re : q * per + 2 * Re + Ce;
-            mi2[q].w = same_next ? (q + 1) * per : q * per + Re;
+        if (tid < kWave) {
+            // the block's missions (at most kGlobalKMax <= 64) on wavefront 0: the block's
+            // vehicles in order (positions are route-ordered) and each mission's vehicle
+            // slot, the number of vehicle changes up to it (a ballot and a popcount)
+            const int q = tid;
+            const bool in = q < kn;
+            const int r = in ? (int)((uint32_t)mi[q].x >> 16) : -1;
+            const bool same_prev = in && q > 0 && ((uint32_t)mi[q - 1].x >> 16) == (uint32_t)r;
+            const bool same_next = in && q + 1 < kn && ((uint32_t)mi[q + 1].x >> 16) == (uint32_t)r;
+            const uint64_t change = __ballot(in && q > 0 && !same_prev);
+            const uint64_t upto = q >= kWave - 1 ? ~0ull : ((1ull << (q + 1)) - 1);
+            const int slot = (int)__popcll(change & upto);
+            if (in) {
+                mi2[q].y = slot;
+                if (!same_prev) rl[slot] = r;
+                if (q == kn - 1) rl[K] = slot + 1;
+                // where the mission's predecessor row and successor column sit in LDS
+                mi2[q].z = same_prev ? (q - 1) * per + 2 * Re : q * per + 2 * Re + Ce;
+                mi2[q].w = same_next ? (q + 1) * per : q * per + Re;
+            }
         }
         __syncthreads();
         const int nd = rl[K];
