@@ -1125,8 +1125,8 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
 // others skip the checks.
 template <typename TE, typename TB>
 __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, const TE *tct,
-                                const TE *tcr, const int4 *ring, int ring_len, char *smem, int K,
-                                int wg, int nwg, int t, int thr, bool use_tabu)
+                                const TE *tcr, const int4 *ring, int ring_len, char *smem, uint64_t *red,
+                                int K, int wg, int nwg, int t, int thr, bool use_tabu)
 {
     constexpr int UR = 8, US = 4;              // relocate and swap loads in flight
     constexpr int ES = (int)sizeof(TE);
@@ -1152,6 +1152,15 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
     int QR = kWave;
     while (QR < nthr && QR * UR < NG) QR <<= 1;
     const int PR = nthr / QR, pr = tid / QR, qr = tid - pr * QR;
+    // the ring's active entries ({vehicle, mission, expiry}), gathered by the first
+    // block's setup into the reduction area (free until the sweeps are done) for all
+    // the workgroup's blocks: at most kActMax of them and a ring of at most one entry
+    // per thread, else each block scans the ring itself (nact < 0)
+    constexpr int kActMax = 120;
+    int4 *act = (int4 *)(red + 16);
+    uint32_t *nact_p = (uint32_t *)(red + 8);
+    const bool listed = use_tabu && ring_len <= nthr;
+    int nact = -1;
     uint64_t best = kKeyNone;
     for (int blk = wg; blk < nblk; blk += nwg) {
         const int i0 = blk * K;
@@ -1163,7 +1172,9 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         if (tid == 0) rl[K + 1] = 0;
         if (use_tabu)
             for (int e = tid; e < kn * V; e += nthr) trow[e] = (TB)0;
-        const int4 ren = (use_tabu && tid < ring_len) ? gld4(ring, tid) : make_int4(0, 0, 0, 0);
+        const bool first = blk == wg;
+        if (listed && first && tid == 0) *nact_p = 0;
+        const int4 ren = (use_tabu && (first || nact < 0) && tid < ring_len) ? gld4(ring, tid) : make_int4(0, 0, 0, 0);
         for (int q = tid; q < 5 * kn; q += nthr) {
             if (q < kn) {
                 const int4 pa = gld4(c.posA, i0 + q);     // {pickup col, successor col, out, m | r << 16}
@@ -1189,6 +1200,10 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
             }
         }
         __syncthreads();
+        if (listed && first && tid < ring_len && ren.z > t) {
+            const uint32_t at = atomicAdd(nact_p, 1u);
+            if (at < (uint32_t)kActMax) act[at] = ren;
+        }
         if (tid < kWave) {
             // the block's missions (at most kGlobalKMax <= 64) on wavefront 0: the block's
             // vehicles in order (positions are route-ordered) and each mission's vehicle
@@ -1212,6 +1227,10 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         }
         __syncthreads();
         const int nd = rl[K];
+        if (listed && first) {
+            nact = (int)*nact_p;
+            if (nact > kActMax) nact = -1;
+        }
         // the travel vectors of the block's missions: 16-byte chunk j of the staged
         // area belongs to mission k = j / P16, whose four vectors (pickup and successor
         // columns, delivery and predecessor rows) follow one another.  Each wavefront
@@ -1241,7 +1260,21 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         // active ring entries: the vehicle column of a block mission (relocates of the
         // mission, swaps of it into a partner's vehicle) and the mission's bit in the
         // row of a block vehicle (swaps of a partner into that vehicle)
-        if (use_tabu) {
+        if (use_tabu && nact >= 0) {
+            // (entry, block mission) pairs over all threads, then (entry, block vehicle)
+            bool hit = false;
+            for (int p = tid; p < nact * kn; p += nthr) {
+                const int e = p / kn, k = p - e * kn;
+                const int4 en = act[e];
+                if ((mi[k].x & 0xFFFF) == en.y) { trow[k * V + en.x] = (TB)en.z; hit = true; }
+            }
+            for (int p = tid; p < nact * nd; p += nthr) {
+                const int e = p / nd, q = p - e * nd;
+                const int4 en = act[e];
+                if (rl[q] == en.x) { atomicOr(&rbits[q * Wm + (en.y >> 5)], 1u << (en.y & 31)); hit = true; }
+            }
+            if (hit) rl[K + 1] = 1;
+        } else if (use_tabu) {
             for (int e0 = 0; e0 < ring_len; e0 += nthr) {
                 const int e = e0 + tid;
                 const int4 en = e0 == 0 ? ren : (e < ring_len ? gld4(ring, e) : make_int4(0, 0, 0, 0));
@@ -1464,7 +1497,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
             thr = g < (int64_t)INT32_MIN ? INT32_MIN : (int)g;
         }
         uint64_t k = eval_staged<TE, TB>(c, I, tc, (const TE *)I.tct, (const TE *)I.tcr, ring, ring_len, smem,
-                                         J.gk, wg, nwg, t, thr, use_tabu);
+                                         red, J.gk, wg, nwg, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) red[wave] = k;
         __syncthreads();
