@@ -169,7 +169,7 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params,
  * wait until a slot and enough budget are free, then join the solves already
  * on the GPU: the device advances every resident solve at least `chunk_iters`
  * iterations per launch (a one-workgroup solve with S move slots per
- * iteration, S < 2^19, runs floor(2^19 / S) times as many, up to the rest of
+ * iteration, S < 2^20, runs floor(2^20 / S) times as many, up to the rest of
  * its budget), so requests that arrive while others run start within one
  * chunk.  Each request's result is the same as at_solve's.
  * at_server_submit returns a ticket; the instance's device arrays are read

@@ -28,7 +28,7 @@ namespace {
 // Move slots per iteration of the reference solve for chunk lengths: a
 // one-workgroup solve with S slots runs max(1, kChunkSlots / S) chunks' worth
 // of iterations per launch.
-constexpr int64_t kChunkSlots = 1 << 19;
+constexpr int64_t kChunkSlots = 1 << 20;
 
 // Requests whose small records (saved-state table, prepared instance, HBM state
 // table) one scatter round places; larger admission batches take several rounds.
