@@ -288,11 +288,12 @@ def test_global_schedule_short_routes(groups):
         assert_same_result(o, g, f"global 24x40 variant {variant} groups {groups}")
 
 
-@pytest.mark.parametrize("tenure,iters", [(0, 60), (1, 60), (40, 30), (300, 400)])
+@pytest.mark.parametrize("tenure,iters", [(0, 60), (1, 60), (40, 30), (80, 200), (300, 400)])
 def test_global_schedule_tenure_edges(tenure, iters):
     """The HBM-resident schedule keeps its tabu state as a ring of the entries of
     the last min(tenure + 1, iterations) iterations: no tenure, tenure 1, a
-    tenure beyond the budget (the ring never wraps) and a ring longer than a
+    tenure beyond the budget (the ring never wraps), more active entries than
+    the per-iteration list holds (tenure 80) and a ring longer than a
     workgroup's threads give the oracle's trajectories, tabu flags included."""
     inst = make_instance(91, 40, 3, 4, 36)
     for variant in (at.AT_TABU, at.AT_NS):
