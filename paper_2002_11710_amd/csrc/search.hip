@@ -1108,8 +1108,8 @@ __device__ void prep_next(const Ctx &o, const Ctx &n, const GMove &mv, const TE 
 }
 
 // Eval of the global schedule: blocks of K (at most kGlobalKMax) consecutive
-// route positions, dealt round-robin to the solve's workgroups (one block per
-// workgroup where LDS allows).  For each block the four travel vectors its
+// route positions, dealt to the solve's workgroups in rounds, every other round
+// in reverse order (one block per workgroup where LDS allows).  For each block the four travel vectors its
 // missions' moves read -- the block column of the pickup and of the successor
 // (rows of the transposed block), the block row of the delivery and of the
 // predecessor (rows of the aligned copy) -- the missions' tabu columns and the
@@ -1162,7 +1162,12 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
     const bool listed = use_tabu && ring_len <= nthr;
     int nact = -1;
     uint64_t best = kKeyNone;
-    for (int blk = wg; blk < nblk; blk += nwg) {
+    // blocks dealt in rounds of nwg, every other round in reverse: a block's swap work
+    // shrinks with its position, so plain round-robin dealing would give the first
+    // workgroups the most work in every round
+    for (int rd = 0; rd * nwg < nblk; ++rd) {
+        const int blk = rd * nwg + ((rd & 1) ? nwg - 1 - wg : wg);
+        if (blk >= nblk) continue;   // uniform over the workgroup
         const int i0 = blk * K;
         const int kn = min(K, M - i0);
         __syncthreads();   // the previous block's LDS reads are done
@@ -1172,7 +1177,7 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
         if (tid == 0) rl[K + 1] = 0;
         if (use_tabu)
             for (int e = tid; e < kn * V; e += nthr) trow[e] = (TB)0;
-        const bool first = blk == wg;
+        const bool first = rd == 0;
         if (listed && first && tid == 0) *nact_p = 0;
         const int4 ren = (use_tabu && (first || nact < 0) && tid < ring_len) ? gld4(ring, tid) : make_int4(0, 0, 0, 0);
         for (int q = tid; q < 5 * kn; q += nthr) {
