@@ -687,6 +687,58 @@ struct GMove {
     int s1, s2, m1, m2;        // swap: the two positions and their missions
 };
 
+// Apply a decoded move to the LDS state with one wavefront.  A relocate moves
+// every entry between the old and the new place by one position (each takes its
+// neighbour's mission and vehicle: only the moved mission changes vehicle), 512
+// positions at a time read into registers and then written, the chunks taken in
+// the direction of the shift so that no chunk reads what an earlier one wrote;
+// the route offsets between the two vehicles move by one.  A swap exchanges two
+// entries.
+__device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int lane)
+{
+    if (mv.kind == 1) {
+        constexpr int U = 8;
+        const int lo = mv.lo, hi = mv.hi, q = mv.q, n = hi - lo + 1;
+        const bool up = mv.dir > 0;
+        for (int c0 = 0; c0 < n; c0 += U * kWave) {
+            int val[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ix = c0 + u * kWave + lane;
+                const int kk = up ? lo + ix : hi - ix;
+                const int src = up ? kk + 1 : kk - 1;
+                val[u] = ix >= n ? 0
+                       : kk == q ? (mv.m | (mv.v << 16)) : ((int)c.seq[src] | ((int)c.rt[src] << 16));
+            }
+            // lanes read what their neighbours then overwrite: keep every read of the
+            // chunk ahead of its writes, and its writes ahead of the next chunk's reads
+            __asm__ volatile("" ::: "memory");
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ix = c0 + u * kWave + lane;
+                if (ix < n) {
+                    const int kk = up ? lo + ix : hi - ix;
+                    const int mm = val[u] & 0xFFFF, r = (int)((uint32_t)val[u] >> 16);
+                    c.seq[kk] = (uint16_t)mm;
+                    c.rt[kk] = (uint16_t)r;
+                    c.pof[mm] = (uint16_t)kk;
+                    c.rof[mm] = (uint16_t)r;
+                }
+            }
+            __asm__ volatile("" ::: "memory");
+        }
+        if (mv.v > mv.rs) for (int r = mv.rs + 1 + lane; r <= mv.v; r += kWave) c.off[r] -= 1;
+        if (mv.v < mv.rs) for (int r = mv.v + 1 + lane; r <= mv.rs; r += kWave) c.off[r] += 1;
+    } else if (mv.kind == 2 && lane == 0) {
+        c.seq[mv.s1] = (uint16_t)mv.m2;
+        c.seq[mv.s2] = (uint16_t)mv.m1;
+        c.pof[mv.m1] = (uint16_t)mv.s2;
+        c.pof[mv.m2] = (uint16_t)mv.s1;
+        c.rof[mv.m1] = (uint16_t)mv.rs;
+        c.rof[mv.m2] = (uint16_t)mv.v;
+    }
+}
+
 template <typename TE, typename TB, bool MULTI>
 __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 {
@@ -699,7 +751,6 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
-    GMove *gm = (GMove *)(c.red + 72);   // the iteration's move, decoded by wave 0
 
     load_instance<TE>(I, c, tc, tid, nthr);
     __syncthreads();
@@ -828,13 +879,14 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                         }
                     }
                 }
-                if (lane == 0) {
-                    *gm = mv;
-                    c.red[66] = wt ? 1 : 0;
-                }
+                if (lane == 0) c.red[66] = wt ? 1 : 0;
+                // apply it before the barrier that publishes the key (the neighbourhood
+                // search stops without applying a move that does not improve)
+                const int dw = (int)((uint32_t)(w >> 32) & 0x7FFFFFFFu) - kDeltaBias;
+                if (use_tabu || dw < 0) apply_wave(c, mv, lane);
             }
         }
-        __syncthreads();
+        __syncthreads();   // the move is decoded and applied
         if (MULTI && c.red[65]) { aborted = true; break; }
         const uint64_t key = c.red[64];
         if (key == kKeyNone) {
@@ -851,38 +903,6 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         if (!use_tabu && d >= 0) { stopped = 1; break; }
         const bool was_tabu = c.red[66] != 0;
         const bool is_swap = idx >= c.R;
-        const GMove mv = *gm;
-        if (!is_swap) {
-            const int m = mv.m, v = mv.v, rs = mv.rs, q = mv.q, lo = mv.lo, hi = mv.hi;
-            const bool up = mv.dir > 0;
-            // each position between the old and the new place takes the mission (and
-            // vehicle: only the moved mission changes vehicle) of its neighbour
-            int32_t *tmp = (int32_t *)c.posB;
-            for (int kk = lo + tid; kk <= hi; kk += nthr) {
-                const int src = up ? kk + 1 : kk - 1;
-                tmp[kk] = (kk == q) ? (m | (v << 16)) : ((int)c.seq[src] | ((int)c.rt[src] << 16));
-            }
-            if (v > rs) for (int r = rs + 1 + tid; r <= v; r += nthr) c.off[r] -= 1;
-            if (v < rs) for (int r = v + 1 + tid; r <= rs; r += nthr) c.off[r] += 1;
-            __syncthreads();
-            for (int kk = lo + tid; kk <= hi; kk += nthr) {
-                const int mm = tmp[kk] & 0xFFFF, r = (int)((uint32_t)tmp[kk] >> 16);
-                c.seq[kk] = (uint16_t)mm;
-                c.rt[kk] = (uint16_t)r;
-                c.pof[mm] = (uint16_t)kk;
-                c.rof[mm] = (uint16_t)r;
-            }
-        } else {
-            if (tid == 0) {
-                c.seq[mv.s1] = (uint16_t)mv.m2;
-                c.seq[mv.s2] = (uint16_t)mv.m1;
-                c.pof[mv.m1] = (uint16_t)mv.s2;
-                c.pof[mv.m2] = (uint16_t)mv.s1;
-                c.rof[mv.m1] = (uint16_t)mv.rs;
-                c.rof[mv.m2] = (uint16_t)mv.v;
-            }
-        }
-        __syncthreads();
         cur += d;
         if (writer && tid == 0 && J.trace) {
             J.tr_move[t] = idx;
