@@ -106,6 +106,47 @@ def test_wide_entries_trajectory(sched, groups):
         assert_same_result(o, g, f"wide entries schedule {sched} groups {groups} variant {variant}")
 
 
+_LONG = {}
+
+
+def _long_shift_case():
+    """1500 missions on 3 vehicles (40 facilities, so the state still fits one
+    workgroup's LDS): the oracle's Tabu trajectory, and how many of its relocates
+    rewrite more than 512 flat positions, moving the mission up and down."""
+    if not _LONG:
+        inst = make_instance(1503, 40, 3, 3, 1500)
+        P = oracle.Problem.from_instance(inst)
+        o = P.solve(variant=oracle.TABU, tenure=7, iters=120)
+        off, seq = P.greedy(0)
+        R = P.M * (P.M + P.V)
+        up = down = 0
+        for idx in o["tr_move"]:
+            if idx < R:
+                m = int(idx) // (P.M + P.V)
+                s = int(np.nonzero(seq == m)[0][0])
+                off, seq = P.apply(off, seq, int(idx))
+                q = int(np.nonzero(seq == m)[0][0])
+                if abs(q - s) + 1 > 512:
+                    up += q > s
+                    down += q < s
+            else:
+                off, seq = P.apply(off, seq, int(idx))
+        assert np.array_equal(seq, o["final_seq"]) and np.array_equal(off, o["final_off"])
+        _LONG.update(inst=inst, o=o, up=up, down=down)
+    return _LONG
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 0), (2, 3)])
+def test_long_relocate_shifts_trajectory(sched, groups):
+    """Relocates that shift more than 512 positions (the LDS schedules apply a
+    move 512 positions at a time, in the direction of the shift): the trajectory
+    still equals the oracle's on the one-workgroup and multi-workgroup schedules."""
+    case = _long_shift_case()
+    assert case["up"] >= 2 and case["down"] >= 2, (case["up"], case["down"])
+    g = at.solve(_dev(case["inst"]), tenure=7, iters=120, schedule=sched, n_groups=groups)
+    assert_same_result(case["o"], g, f"1500 missions sched {sched} groups {groups}")
+
+
 # ------------------------------------------------------------------ whole trajectories
 
 def test_small_workload_tabu_trajectory():
