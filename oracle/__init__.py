@@ -70,12 +70,21 @@ def lib():
                                i64p, i64p, i32p, i32p, u32p, i32p, i64p, u8p]
         L.or_num_slots.argtypes = [C.c_int32, C.c_int32]
         L.or_num_slots.restype = C.c_int64
+        L.or_splitmix64.argtypes = [C.c_uint64, C.c_int32, u64p]
+        L.or_splitmix64.restype = None
         _lib = L
     return _lib
 
 
 def _ptr(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
+
+
+def splitmix64(seed: int, n: int) -> list:
+    """The first n outputs of the oracle's SplitMix64(seed)."""
+    out = np.empty(max(n, 1), dtype=np.uint64)
+    lib().or_splitmix64(C.c_uint64(seed & ((1 << 64) - 1)), n, _ptr(out, C.c_uint64))
+    return [int(x) for x in out[:n]]
 
 
 def travel(lat, lon, speed_kmh: float = 260.0) -> np.ndarray:

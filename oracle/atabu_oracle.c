@@ -40,9 +40,16 @@
  * enumeration of every solution (and a Held-Karp subset DP) for the optimum
  * the search must not beat; or_delta_inc against or_delta_def on every move of
  * random solutions; route invariants after every step; the neighbourhood
- * search stopping only at a true local optimum.  The exact trajectory of
- * or_solve (which move each iteration takes) is parity unpinned beyond those
- * properties: the paper prints no worked trajectory to check it against.
+ * search stopping only at a true local optimum.  SplitMix64 against the
+ * generator's published reference outputs; the greedy start against a
+ * hand-worked shuffled order, a hand-computed instance where the route's old
+ * return leg decides the vehicle, and exact ties; each step's tabu writes
+ * (exactly the moved missions' entries for the vehicles they left, at
+ * t + tenure), the (mission, vehicle) entries that make a slot tabu, strict
+ * aspiration, the trace flags, and the choice of the admissible move with the
+ * smallest by-definition delta, ties to the smallest slot index.  A whole
+ * trajectory is the composition of those pinned steps; the paper prints no
+ * worked trajectory to compare one against.
  */
 #define _GNU_SOURCE 1
 #include <math.h>
@@ -344,8 +351,11 @@ static int check_inst(const or_inst *in)
     }
     for (int32_t v = 0; v < in->V; ++v)
         if (in->b[v] < 0 || in->b[v] >= in->L) return OR_EINVAL;
+    /* the key packs delta + 2^30 into 31 bits; a delta sums at most three
+     * travel times minus three others, so times below 2^27 (max T * 8 < 2^30)
+     * keep every delta inside that field */
     for (int64_t k = 0; k < (int64_t)in->L * in->L; ++k)
-        if (in->T[k] < 0 || in->T[k] >= (1 << 23)) return OR_ERANGE;
+        if (in->T[k] < 0 || in->T[k] >= (1 << 27)) return OR_ERANGE;
     return OR_OK;
 }
 
@@ -370,6 +380,14 @@ static uint64_t splitmix64_next(uint64_t *state)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
+}
+
+/* Public: the first n outputs of SplitMix64(seed) (pinned to the generator's
+ * published reference outputs). */
+void or_splitmix64(uint64_t seed, int32_t n, uint64_t *out)
+{
+    uint64_t st = seed;
+    for (int32_t i = 0; i < n; ++i) out[i] = splitmix64_next(&st);
 }
 
 /* Algorithm 1, generalised (no deadlines, flight limit or vehicle types):
