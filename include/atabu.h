@@ -92,7 +92,9 @@ typedef struct at_params {
 
 /* Results of one solve.  Arrays are device memory supplied by the caller;
  * scalars are written by the library (host).  The routes are the best
- * solution seen (the greedy start counts, best_iter = -1).  Route v holds
+ * solution seen (the greedy start counts, best_iter = -1); final_off and
+ * final_seq, when given, receive the routes the search ends on, in the same
+ * layout.  Route v holds
  * missions route_seq[route_off[v] .. route_off[v+1]) in flying order;
  * route_of[m] is the vehicle of mission m.  Trace record t (t < iters_done):
  * the slot index of the applied move (0xFFFFFFFF when no move exists), its
@@ -107,6 +109,8 @@ typedef struct at_result {
     int32_t *route_off;     /* device, V+1 */
     int32_t *route_seq;     /* device, M */
     int32_t *route_of;      /* device, M (may be NULL) */
+    int32_t *final_off;     /* device, V+1 (may be NULL): routes after the last iteration */
+    int32_t *final_seq;     /* device, M (NULL when final_off is NULL) */
     uint32_t *tr_move;      /* device, max_iters (NULL when trace == 0) */
     int32_t *tr_delta;      /* device, max_iters */
     int64_t *tr_obj;        /* device, max_iters */
@@ -121,14 +125,29 @@ typedef struct at_result {
                                one launch per kernel class; every solve of it reports that) */
 } at_result;
 
-/* Eq (1): travel-time matrix of n points.  lat_deg, lon_deg: device, n
- * doubles (degrees); travel: device, n*n int32 written row-major with
- * round-half-away-from-zero of 2*6371*asin(sqrt(min(1, a))) * 3600 / speed,
- * a = sin^2(dlat/2) + cos(lat_i) cos(lat_j) sin^2(dlon/2), in FP64 without
- * contraction.  Asynchronous on `stream`.  AT_EINVAL if n < 1, n > 65535 or
- * speed <= 0. */
+/* Eq (1) (Section 3 of the paper): travel-time matrix of n points, on the
+ * host.  lat_deg, lon_deg: host, n doubles (degrees: latitude and longitude
+ * are the paper's row and column coordinates phi, psi); travel: host, n*n
+ * int32 written row-major, travel[i*n + j] = round-half-away-from-zero of
+ * 2*6371*asin(sqrt(min(1, a))) * 3600 / speed_kmh seconds with
+ * a = sin^2((phi_j - phi_i)/2) + cos(phi_i) cos(phi_j) sin^2((psi_j - psi_i)/2),
+ * in FP64 with the system libm, without contraction, in that order.  Every
+ * ordered pair is computed (nothing is mirrored); the diagonal is 0.
+ * AT_EINVAL if n < 1, n > 65535, a pointer is null or speed_kmh is not a
+ * positive finite number; AT_ERANGE if a time does not fit int32 (travel is
+ * then unspecified).  Synchronous; touches no device. */
 int at_build_travel(int32_t n, const double *lat_deg, const double *lon_deg, double speed_kmh,
-                    int32_t *travel, void *stream);
+                    int32_t *travel);
+
+/* The same matrix computed on the device, one thread per ordered pair: lat_deg,
+ * lon_deg and travel are device pointers; asynchronous on `stream`.  Its
+ * sin/cos/asin/sqrt are the device math library's, which may round a
+ * different way than the host libm in rare cases, so a time within an ulp of a
+ * half second could differ by one from at_build_travel; a time above INT32_MAX
+ * is written as INT32_MAX (the solve then rejects it with AT_ERANGE).  Same
+ * argument errors as at_build_travel. */
+int at_build_travel_device(int32_t n, const double *lat_deg, const double *lon_deg,
+                           double speed_kmh, int32_t *travel, void *stream);
 
 /* Bytes of device workspace at_solve_batch needs for these instances and
  * parameters (n_inst entries each, n_restarts solves per instance).  0 on bad
@@ -186,6 +205,16 @@ int at_server_submit(void *server, const at_instance *inst, const at_params *par
 int at_server_progress(void *server, int32_t *n_active);
 int at_server_poll(void *server, uint64_t ticket, at_result *out);
 int at_server_destroy(void *server);
+
+/* Release what the library holds between calls: the internal streams on
+ * which the one-workgroup launches of a batch's different size classes run
+ * concurrently (created on first use, each synchronised before it is
+ * destroyed).  Optional; call it with no other library call in flight, for
+ * example before the process exits, so that nothing of the library is left
+ * for the runtime's exit-time teardown.  A later call creates them again.
+ * Servers are released by at_server_destroy, not here.  AT_EDEVICE if a
+ * synchronisation or destruction fails. */
+int at_shutdown(void);
 
 /* Thread-local text of the last error returned on this thread. */
 const char *at_last_error(void);

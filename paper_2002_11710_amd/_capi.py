@@ -14,9 +14,10 @@ SCHED_AUTO, SCHED_WG, SCHED_MULTI, SCHED_GLOBAL = 0, 1, 2, 3
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libatabu.so")
 
-_EXPORTS = ("at_build_travel", "at_workspace_size", "at_solve", "at_solve_batch",
-            "at_debug_eval_moves", "at_server_create", "at_server_submit",
-            "at_server_progress", "at_server_poll", "at_server_destroy", "at_last_error")
+_EXPORTS = ("at_build_travel", "at_build_travel_device", "at_workspace_size", "at_solve",
+            "at_solve_batch", "at_debug_eval_moves", "at_server_create", "at_server_submit",
+            "at_server_progress", "at_server_poll", "at_server_destroy", "at_shutdown",
+            "at_last_error")
 
 
 class AtError(RuntimeError):
@@ -40,7 +41,7 @@ class _Params(C.Structure):
 
 class _Result(C.Structure):
     _fields_ = [("route_off", C.c_void_p), ("route_seq", C.c_void_p), ("route_of", C.c_void_p),
-                ("tr_move", C.c_void_p), ("tr_delta", C.c_void_p), ("tr_obj", C.c_void_p),
+                ("final_off", C.c_void_p), ("final_seq", C.c_void_p), ("tr_move", C.c_void_p), ("tr_delta", C.c_void_p), ("tr_obj", C.c_void_p),
                 ("tr_flags", C.c_void_p), ("best_obj", C.c_int64), ("final_obj", C.c_int64),
                 ("iters_done", C.c_int32), ("best_iter", C.c_int32), ("status", C.c_int32),
                 ("search_ms", C.c_float)]
@@ -62,7 +63,8 @@ def lib():
             import torch  # noqa: F401
             L = C.CDLL(lib_path)
             vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
-            L.at_build_travel.argtypes = [i32, vp, vp, C.c_double, vp, vp]
+            L.at_build_travel.argtypes = [i32, vp, vp, C.c_double, vp]
+            L.at_build_travel_device.argtypes = [i32, vp, vp, C.c_double, vp, vp]
             L.at_workspace_size.argtypes = [i32, C.POINTER(_Instance), C.POINTER(_Params), i32]
             L.at_workspace_size.restype = C.c_size_t
             L.at_solve.argtypes = [C.POINTER(_Instance), C.POINTER(_Params), vp, C.c_size_t, vp,
@@ -89,6 +91,12 @@ def symbols():
     return [n for n in _EXPORTS if hasattr(L, n)]
 
 
+def shutdown():
+    """Release the library's internal streams (at_shutdown); see include/atabu.h."""
+    if _lib is not None:
+        _check(_lib.at_shutdown())
+
+
 def _check(rc: int):
     if rc != AT_OK:
         msg = lib().at_last_error()
@@ -112,15 +120,29 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
-def build_travel(lat, lon, speed_kmh: float = 260.0, stream=None):
-    """Eq (1) on the device: (n, n) int32 seconds from FP64 lat/lon tensors (degrees)."""
+def build_travel(lat, lon, speed_kmh: float = 260.0):
+    """Eq (1) on the host (at_build_travel): (n, n) int32 seconds as a numpy array
+    from FP64 latitudes and longitudes in degrees."""
+    lat = np.ascontiguousarray(lat, dtype=np.float64)
+    lon = np.ascontiguousarray(lon, dtype=np.float64)
+    n = int(lat.shape[0])
+    if lon.shape[0] != n:
+        raise AtError(AT_EINVAL, "lat and lon differ in length")
+    out = np.empty((n, n), dtype=np.int32)
+    _check(lib().at_build_travel(n, lat.ctypes.data_as(C.c_void_p), lon.ctypes.data_as(C.c_void_p),
+                                 float(speed_kmh), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def build_travel_device(lat, lon, speed_kmh: float = 260.0, stream=None):
+    """Eq (1) on the device (at_build_travel_device): (n, n) int32 tensor."""
     torch = _torch()
     lat = torch.as_tensor(lat, dtype=torch.float64).contiguous().cuda()
     lon = torch.as_tensor(lon, dtype=torch.float64).contiguous().cuda()
     n = lat.shape[0]
     out = torch.empty((n, n), dtype=torch.int32, device=lat.device)
-    _check(lib().at_build_travel(n, _dptr(lat), _dptr(lon), float(speed_kmh), _dptr(out),
-                                 _stream_ptr(stream)))
+    _check(lib().at_build_travel_device(n, _dptr(lat), _dptr(lon), float(speed_kmh), _dptr(out),
+                                        _stream_ptr(stream)))
     return out
 
 
@@ -138,14 +160,15 @@ class DeviceInstance:
         self.n_vehicles = int(self.vehicle_loc.shape[0])
 
     @classmethod
-    def from_coords(cls, lat, lon, pickup, delivery, vehicle_loc, speed_kmh=260.0, stream=None):
-        return cls(build_travel(lat, lon, speed_kmh, stream), pickup, delivery, vehicle_loc)
+    def from_coords(cls, lat, lon, pickup, delivery, vehicle_loc, speed_kmh=260.0):
+        """Eq (1) on the host (at_build_travel), then the matrix is uploaded."""
+        return cls(build_travel(lat, lon, speed_kmh), pickup, delivery, vehicle_loc)
 
     @classmethod
-    def from_instance(cls, inst, speed_kmh=260.0, stream=None):
-        """From a gen.instances.Instance: coordinates uploaded, Eq (1) on the device."""
+    def from_instance(cls, inst, speed_kmh=260.0):
+        """From a gen.instances.Instance (coordinates, missions, vehicle bases)."""
         return cls.from_coords(inst.lat, inst.lon, inst.pickup, inst.delivery, inst.vehicle_loc,
-                               speed_kmh, stream)
+                               speed_kmh)
 
     def c_struct(self) -> _Instance:
         return _Instance(self.n_locs, self.travel.data_ptr(), self.n_missions,
@@ -165,7 +188,9 @@ def _alloc_result(M: int, V: int, iters: int, trace: bool, device):
     torch = _torch()
     r = dict(route_off=torch.empty(V + 1, dtype=torch.int32, device=device),
              route_seq=torch.empty(max(M, 1), dtype=torch.int32, device=device),
-             route_of=torch.empty(max(M, 1), dtype=torch.int32, device=device))
+             route_of=torch.empty(max(M, 1), dtype=torch.int32, device=device),
+             final_off=torch.empty(V + 1, dtype=torch.int32, device=device),
+             final_seq=torch.empty(max(M, 1), dtype=torch.int32, device=device))
     if trace:
         n = max(iters, 1)
         r.update(tr_move=torch.empty(n, dtype=torch.int32, device=device),
@@ -178,6 +203,8 @@ def _alloc_result(M: int, V: int, iters: int, trace: bool, device):
 def _c_result(bufs) -> _Result:
     g = bufs.get
     return _Result(g("route_off").data_ptr(), g("route_seq").data_ptr(), g("route_of").data_ptr(),
+                   g("final_off").data_ptr() if "final_off" in bufs else None,
+                   g("final_seq").data_ptr() if "final_seq" in bufs else None,
                    g("tr_move").data_ptr() if "tr_move" in bufs else None,
                    g("tr_delta").data_ptr() if "tr_delta" in bufs else None,
                    g("tr_obj").data_ptr() if "tr_obj" in bufs else None,
@@ -188,6 +215,8 @@ def _finish(bufs, res: _Result, M: int):
     out = dict(bufs)
     out["route_seq"] = bufs["route_seq"][:M]
     out["route_of"] = bufs["route_of"][:M]
+    if "final_seq" in bufs:
+        out["final_seq"] = bufs["final_seq"][:M]
     k = res.iters_done
     for name in ("tr_move", "tr_delta", "tr_obj", "tr_flags"):
         if name in bufs:

@@ -352,6 +352,8 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.out_off = h.out.route_off;
     j.out_seq = h.out.route_seq;
     j.out_of = h.out.route_of;
+    j.fin_off = h.out.final_off;
+    j.fin_seq = h.out.final_off ? h.out.final_seq : nullptr;
     if (j.trace) {
         j.tr_move = h.out.tr_move;
         j.tr_delta = h.out.tr_delta;
@@ -390,15 +392,29 @@ int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> 
 // Internal streams on which the one-workgroup-per-job launches of different
 // size classes run concurrently (forked from and joined back to the caller's
 // stream with events).  Default priority, created once.
+static hipStream_t g_class_pool[kMaxClasses] = {};
+
 static hipStream_t class_stream(int k)
 {
-    static hipStream_t pool[kMaxClasses] = {};
-    static bool made[kMaxClasses] = {};
-    if (!made[k]) {
-        if (hipStreamCreateWithFlags(&pool[k], hipStreamNonBlocking) != hipSuccess) return nullptr;
-        made[k] = true;
+    if (!g_class_pool[k] && hipStreamCreateWithFlags(&g_class_pool[k], hipStreamNonBlocking) != hipSuccess) {
+        g_class_pool[k] = nullptr;
+        return nullptr;
     }
-    return pool[k];
+    return g_class_pool[k];
+}
+
+// Destroy the class streams (at_shutdown): each is synchronised first.
+int release_class_streams()
+{
+    int rc = AT_OK;
+    for (int k = 0; k < kMaxClasses; ++k) {
+        if (!g_class_pool[k]) continue;
+        hipError_t e = hipStreamSynchronize(g_class_pool[k]);
+        if (e == hipSuccess) e = hipStreamDestroy(g_class_pool[k]);
+        if (e != hipSuccess && rc == AT_OK) rc = hip_fail(e, "class stream release");
+        g_class_pool[k] = nullptr;
+    }
+    return rc;
 }
 
 // Launch every job of `dj` (device table in the order of `order`).  Jobs of
@@ -667,6 +683,9 @@ static int solve_common(int32_t n_inst, const at_instance *insts, const at_param
     for (int64_t k = 0; k < nj; ++k)
         if (!out[k].route_off || (insts[k / n_restarts].n_missions > 0 && !out[k].route_seq))
             return fail(AT_EINVAL, "solve %lld: null route output", (long long)k);
+    for (int64_t k = 0; k < nj; ++k)
+        if (out[k].final_off && insts[k / n_restarts].n_missions > 0 && !out[k].final_seq)
+            return fail(AT_EINVAL, "solve %lld: final_off without final_seq", (long long)k);
     WsPlan p = plan_ws(n_inst, insts, params, n_restarts);
     if (ws_bytes < p.end) return fail(AT_ENOMEM, "workspace %zu bytes, need %zu", ws_bytes, p.end);
     hipStream_t s = (hipStream_t)stream;
@@ -700,8 +719,21 @@ extern "C" {
 
 const char *at_last_error(void) { return last_error(); }
 
+int at_shutdown(void) { return release_class_streams(); }
+
 int at_build_travel(int32_t n, const double *lat_deg, const double *lon_deg, double speed_kmh,
-                    int32_t *travel, void *stream)
+                    int32_t *travel)
+{
+    if (n < 1 || n > kMaxLocs) return fail(AT_EINVAL, "n %d outside [1, %d]", n, kMaxLocs);
+    if (!(speed_kmh > 0.0) || !std::isfinite(speed_kmh)) return fail(AT_EINVAL, "speed must be positive");
+    if (!lat_deg || !lon_deg || !travel) return fail(AT_EINVAL, "null pointer");
+    return host_travel(n, lat_deg, lon_deg, speed_kmh, travel)
+               ? AT_OK
+               : fail(AT_ERANGE, "a travel time does not fit int32 seconds");
+}
+
+int at_build_travel_device(int32_t n, const double *lat_deg, const double *lon_deg, double speed_kmh,
+                           int32_t *travel, void *stream)
 {
     if (n < 1 || n > kMaxLocs) return fail(AT_EINVAL, "n %d outside [1, %d]", n, kMaxLocs);
     if (!(speed_kmh > 0.0) || !std::isfinite(speed_kmh)) return fail(AT_EINVAL, "speed must be positive");

@@ -132,6 +132,7 @@ struct JobDev {
     int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
     uint64_t seed;
     int32_t *out_off, *out_seq, *out_of;
+    int32_t *fin_off, *fin_seq;       // routes after the last iteration (may be null)
     uint32_t *tr_move;
     int32_t *tr_delta;
     int64_t *tr_obj;
@@ -218,6 +219,8 @@ __host__ __device__ inline int64_t n_slots(int64_t M, int64_t V) { return M * (M
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_travel(int32_t n, const double *lat, const double *lon, double speed,
                          int32_t *out, hipStream_t s);
+// Eq (1) on the host (false if a time does not fit int32)
+bool host_travel(int32_t n, const double *lat, const double *lon, double speed, int32_t *out);
 // chunks of the travel scan of one instance (returned) and of its block fill (out)
 int64_t prepare_chunks(const InstDev &h, int64_t *fill_chunks);
 hipError_t launch_prepare(InstDev *insts, int32_t n, int64_t scan_chunks, int64_t fill_chunks, hipStream_t s);

@@ -664,15 +664,22 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
     return acc + svc_sum;
 }
 
-// write the current routes as the best solution
-__device__ __forceinline__ void snapshot(const Ctx &c, const JobDev &J, int tid, int nthr)
+// write the current routes (and, when `of` is given, each mission's vehicle)
+__device__ __forceinline__ void write_routes(const Ctx &c, int32_t *off, int32_t *seq, int32_t *of,
+                                             int tid, int nthr)
 {
     for (int i = tid; i < c.M; i += nthr) {
         const int m = c.seq[i];
-        J.out_seq[i] = m;
-        if (J.out_of) J.out_of[m] = c.rt[i];
+        seq[i] = m;
+        if (of) of[m] = c.rt[i];
     }
-    for (int v = tid; v <= c.V; v += nthr) J.out_off[v] = c.off[v];
+    for (int v = tid; v <= c.V; v += nthr) off[v] = c.off[v];
+}
+
+// write the current routes as the best solution
+__device__ __forceinline__ void snapshot(const Ctx &c, const JobDev &J, int tid, int nthr)
+{
+    write_routes(c, J.out_off, J.out_seq, J.out_of, tid, nthr);
 }
 
 // ---------------------------------------------------------------------------
@@ -917,6 +924,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         }
     }
     if (!writer) return;
+    if (J.fin_off && !aborted) write_routes(c, J.fin_off, J.fin_seq, nullptr, tid, nthr);
     if (tid == 0) {
         J.scal->best_obj = best;
         J.scal->final_obj = cur;
@@ -1605,6 +1613,7 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
     }
     if (!writer) return;
     if (pending && !aborted) snapshot(global_ctx(I, B, p, red), J, tid, nthr);
+    if (J.fin_off && !aborted) write_routes(global_ctx(I, B, p, red), J.fin_off, J.fin_seq, nullptr, tid, nthr);
     if (tid == 0) {
         J.scal->best_obj = best;
         J.scal->final_obj = cur;

@@ -116,6 +116,7 @@ size_t request_bytes(const at_instance &in, const at_params &pr)
     b += inst_bytes(in, may_need_global(in, pr));
     b += al256(4 * M) + al256(4 * (V + 1)) + al256(4 * M * V);          // saved routes + tabu
     b += al256(4 * (V + 1)) + 2 * al256(4 * (M ? M : 1));                // best routes
+    b += al256(4 * (V + 1)) + al256(4 * (M ? M : 1));                    // final routes
     if (pr.trace) {
         const size_t n = (size_t)(pr.max_iters > 0 ? pr.max_iters : 1);
         b += al256(4 * n) * 2 + al256(8 * n) + al256(n);
@@ -177,6 +178,8 @@ struct Server {
         r.out.route_off = (int32_t *)p; p += al256(4 * (V + 1));
         r.out.route_seq = (int32_t *)p; p += al256(4 * (M ? M : 1));
         r.out.route_of = (int32_t *)p; p += al256(4 * (M ? M : 1));
+        r.out.final_off = (int32_t *)p; p += al256(4 * (V + 1));
+        r.out.final_seq = (int32_t *)p; p += al256(4 * (M ? M : 1));
         if (r.pr.trace) {
             const size_t n = (size_t)(r.pr.max_iters > 0 ? r.pr.max_iters : 1);
             r.out.tr_move = (uint32_t *)p; p += al256(4 * n);
@@ -472,6 +475,8 @@ int at_server_poll(void *server, uint64_t ticket, at_result *out)
         if (out->route_off) e = hipMemcpyAsync(out->route_off, r->out.route_off, 4 * (V + 1), hipMemcpyDeviceToDevice, sv->s);
         if (e == hipSuccess && out->route_seq && M) e = hipMemcpyAsync(out->route_seq, r->out.route_seq, 4 * M, hipMemcpyDeviceToDevice, sv->s);
         if (e == hipSuccess && out->route_of && M) e = hipMemcpyAsync(out->route_of, r->out.route_of, 4 * M, hipMemcpyDeviceToDevice, sv->s);
+        if (e == hipSuccess && out->final_off) e = hipMemcpyAsync(out->final_off, r->out.final_off, 4 * (V + 1), hipMemcpyDeviceToDevice, sv->s);
+        if (e == hipSuccess && out->final_off && out->final_seq && M) e = hipMemcpyAsync(out->final_seq, r->out.final_seq, 4 * M, hipMemcpyDeviceToDevice, sv->s);
         const size_t n = (size_t)r->last.iters_done;
         if (e == hipSuccess && r->pr.trace && n) {
             if (out->tr_move) e = hipMemcpyAsync(out->tr_move, r->out.tr_move, 4 * n, hipMemcpyDeviceToDevice, sv->s);

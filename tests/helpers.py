@@ -46,3 +46,17 @@ def assert_same_result(o, g, label=""):
     assert g["best_iter"] == o["best_iter"], (label, g["best_iter"], o["best_iter"])
     assert np.array_equal(g["route_off"], o["best_off"]), label
     assert np.array_equal(g["route_seq"], o["best_seq"]), label
+    if "route_of" in g:
+        assert np.array_equal(g["route_of"], route_of(o["best_off"], o["best_seq"])), label
+    if "final_off" in g:
+        assert np.array_equal(g["final_off"], o["final_off"]), label
+        assert np.array_equal(g["final_seq"], o["final_seq"]), label
+
+
+def route_of(off, seq):
+    """Vehicle of every mission of a flattened solution (off: V+1, seq: M)."""
+    off = np.asarray(off)
+    out = np.empty(len(seq), dtype=np.int32)
+    for v in range(len(off) - 1):
+        out[np.asarray(seq[off[v]:off[v + 1]], dtype=np.int64)] = v
+    return out

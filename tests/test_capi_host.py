@@ -88,6 +88,61 @@ def test_workspace_too_small_and_build_travel_args():
                               C.byref(res))
     assert rc == _capi.AT_ENOMEM
     L = _capi.lib()
-    assert L.at_build_travel(0, 0x1, 0x2, 260.0, 0x3, None) == _capi.AT_EINVAL
-    assert L.at_build_travel(5, 0x1, 0x2, -1.0, 0x3, None) == _capi.AT_EINVAL
-    assert L.at_build_travel(5, None, 0x2, 260.0, 0x3, None) == _capi.AT_EINVAL
+    assert L.at_build_travel(0, 0x1, 0x2, 260.0, 0x3) == _capi.AT_EINVAL
+    assert L.at_build_travel(5, 0x1, 0x2, -1.0, 0x3) == _capi.AT_EINVAL
+    assert L.at_build_travel(5, 0x1, 0x2, float("nan"), 0x3) == _capi.AT_EINVAL
+    assert L.at_build_travel(5, None, 0x2, 260.0, 0x3) == _capi.AT_EINVAL
+    assert L.at_build_travel_device(0, 0x1, 0x2, 260.0, 0x3, None) == _capi.AT_EINVAL
+    assert L.at_build_travel_device(5, 0x1, 0x2, 0.0, 0x3, None) == _capi.AT_EINVAL
+
+
+def _workload_coords():
+    """Coordinates of every workload: the 3x12 instance and its 2x6 twin, the
+    16x400 instance, a sample of the uneven batch, the serving stream's largest
+    request (M = 2000) and two others, and the 256x10000 stress instance."""
+    from gen.instances import (batch_instance, batch_specs, brute_twin, m400_instance,
+                               make_instance, serve_specs, small_instance, stress_instance)
+    out = [("3x12", small_instance(0)), ("2x6", brute_twin(0)), ("16x400", m400_instance(0))]
+    for spec in batch_specs(64)[::16]:
+        out.append((f"batch {spec['index']}", batch_instance(spec)))
+    specs = serve_specs(2000)
+    big = max(specs, key=lambda s: s["n_missions"])
+    assert big["n_missions"] == 2000
+    for s in (specs[0], specs[1], big):
+        out.append((f"serve {s['index']}", make_instance(s["seed"], s["n_fac"], s["n_bases"],
+                                                         s["n_vehicles"], s["n_missions"])))
+    out.append(("stress", stress_instance(0)))
+    return out
+
+
+def test_host_travel_equals_oracle_on_every_workload():
+    """Eq (1) on the host through the C ABI (at_build_travel, FP64, no
+    contraction, host libm) equals the oracle's matrix bit for bit on every
+    workload."""
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    import numpy as np
+
+    import oracle
+    for name, inst in _workload_coords():
+        T = at.build_travel(inst.lat, inst.lon)
+        assert T.dtype == np.int32 and T.shape == (inst.n_locs, inst.n_locs)
+        assert np.array_equal(T, oracle.travel(inst.lat, inst.lon)), name
+    # 5 km/h gives times above 65535 s (32-bit compact entries in the search)
+    inst = _workload_coords()[2][1]
+    assert np.array_equal(at.build_travel(inst.lat, inst.lon, 5.0),
+                          oracle.travel(inst.lat, inst.lon, 5.0))
+
+
+def test_host_travel_range():
+    """A time that does not fit int32 seconds is rejected instead of wrapping."""
+    if not os.path.exists(_capi.lib_path):
+        pytest.skip("libatabu.so not built")
+    import numpy as np
+    lat = np.array([42.0, 57.0])
+    lon = np.array([-95.0, -75.0])
+    with pytest.raises(_capi.AtError) as e:
+        at.build_travel(lat, lon, 1e-3)
+    assert e.value.code == _capi.AT_ERANGE
+    T = at.build_travel(lat, lon, 260.0)
+    assert T[0, 0] == 0 and T[1, 1] == 0 and T[0, 1] == T[1, 0] > 0

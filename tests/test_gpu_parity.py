@@ -24,16 +24,17 @@ def _dev(inst):
 # ------------------------------------------------------------------ Eq (1)
 
 @pytest.mark.parametrize("maker", [small_instance, brute_twin, m400_instance, stress_instance])
-def test_travel_matrix_bit_exact(maker):
+def test_device_travel_matrix_bit_exact(maker):
+    """The device variant of Eq (1) (at_build_travel_device) on the workloads."""
     inst = maker(0)
-    T = at.build_travel(inst.lat, inst.lon).cpu().numpy()
+    T = at.build_travel_device(inst.lat, inst.lon).cpu().numpy()
     assert np.array_equal(T, oracle.travel(inst.lat, inst.lon))
 
 
-def test_travel_matrix_batch_sample():
+def test_device_travel_matrix_batch_sample():
     for spec in batch_specs(64)[::8]:
         inst = batch_instance(spec)
-        T = at.build_travel(inst.lat, inst.lon).cpu().numpy()
+        T = at.build_travel_device(inst.lat, inst.lon).cpu().numpy()
         assert np.array_equal(T, oracle.travel(inst.lat, inst.lon)), spec["index"]
 
 
@@ -254,6 +255,18 @@ def test_cooperative_schedules_tenure_and_aspiration(sched, groups):
         _, o = oracle_solve(inst, tenure=tenure, iters=200, aspiration=asp)
         g = at.solve(dev, tenure=tenure, iters=200, aspiration=bool(asp), schedule=sched, n_groups=groups)
         assert_same_result(o, g, f"schedule {sched} groups {groups} tenure {tenure} aspiration {asp}")
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 0), (2, 3), (3, 4)])
+def test_all_tabu_fallback_every_schedule(sched, groups):
+    """A tenure longer than the budget (300 over 400 iterations on 4 vehicles x
+    36 missions) makes every move tabu for many iterations: the best blocked
+    move is taken (trace flag bit 2) on every schedule, as in the oracle."""
+    inst = make_instance(91, 40, 3, 4, 36)
+    _, o = oracle_solve(inst, tenure=300, iters=400)
+    assert int(np.count_nonzero(o["tr_flags"] & 4)) > 50
+    g = at.solve(_dev(inst), tenure=300, iters=400, schedule=sched, n_groups=groups)
+    assert_same_result(o, g, f"fallback schedule {sched} groups {groups}")
 
 
 def test_bad_device_inputs_are_rejected():

@@ -44,7 +44,8 @@ def _same(a, b, label):
     a, b = gpu_to_np(a), gpu_to_np(b)
     for k in ("best_obj", "final_obj", "iters_done", "best_iter", "status"):
         assert a[k] == b[k], (label, k, a[k], b[k])
-    for k in ("route_off", "route_seq", "tr_move", "tr_delta", "tr_obj", "tr_flags"):
+    for k in ("route_off", "route_seq", "route_of", "final_off", "final_seq", "tr_move", "tr_delta",
+              "tr_obj", "tr_flags"):
         assert np.array_equal(a[k], b[k]), (label, k)
 
 
