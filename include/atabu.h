@@ -161,6 +161,24 @@ size_t at_workspace_size(int32_t n_inst, const at_instance *insts, const at_para
 int at_solve(const at_instance *inst, const at_params *params, void *ws, size_t ws_bytes,
              void *stream, at_result *out);
 
+/* at_solve for callers that cannot allocate memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation, code being
+ * prepared for graph capture).  Same instance, parameters, results and
+ * errors as at_solve, without a workspace argument: the workspace is a fixed
+ * 64 MiB device array inside the library (one per device, created when the
+ * library's code is loaded on that device and held until the process ends).
+ * Nothing is allocated on the device or in pinned host memory, and no stream
+ * or event is created; search_ms is reported as 0.  A solve whose workspace
+ * (at_workspace_size(1, inst, params, 1)) exceeds 64 MiB returns AT_ENOMEM
+ * before touching the device (the 10 000-mission, 2200-location stress
+ * instance needs 57 MiB; a 16 000-mission instance on 4300 locations would
+ * need over 200 MiB).  The array keeps the last call's contents and every call sets up
+ * what it reads; calls on one device share it, so calls from several host
+ * threads are serialised by a per-device lock (each is blocking on its
+ * stream), and work on the device that overlaps a call must not use it. */
+int at_solve_noalloc(const at_instance *inst, const at_params *params, void *stream,
+                     at_result *out);
+
 /* Solve n_inst instances x n_restarts restarts.  params[i] applies to
  * instance i; restart r of instance i starts from restart_seed 0 when r == 0
  * and from params[i].restart_seed + r otherwise.  out has n_inst*n_restarts

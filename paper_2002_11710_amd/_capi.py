@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libatabu.so")
 
 _EXPORTS = ("at_build_travel", "at_build_travel_device", "at_workspace_size", "at_solve",
-            "at_solve_batch", "at_debug_eval_moves", "at_server_create", "at_server_submit",
+            "at_solve_noalloc", "at_solve_batch", "at_debug_eval_moves", "at_server_create", "at_server_submit",
             "at_server_progress", "at_server_poll", "at_server_destroy", "at_shutdown",
             "at_last_error")
 
@@ -69,6 +69,8 @@ def lib():
             L.at_workspace_size.restype = C.c_size_t
             L.at_solve.argtypes = [C.POINTER(_Instance), C.POINTER(_Params), vp, C.c_size_t, vp,
                                    C.POINTER(_Result)]
+            L.at_solve_noalloc.argtypes = [C.POINTER(_Instance), C.POINTER(_Params), vp,
+                                           C.POINTER(_Result)]
             L.at_solve_batch.argtypes = [i32, C.POINTER(_Instance), C.POINTER(_Params), i32, vp,
                                          C.c_size_t, vp, C.POINTER(_Result)]
             L.at_debug_eval_moves.argtypes = [C.POINTER(_Instance), C.POINTER(_Params), vp, vp, vp,
@@ -256,6 +258,22 @@ def solve(inst: DeviceInstance, variant=AT_TABU, tenure=7, iters=500, aspiration
     res = _c_result(bufs)
     _check(lib().at_solve(C.byref(ci), C.byref(pr), _dptr(ws), ws.numel(), _stream_ptr(stream),
                           C.byref(res)))
+    return _finish(bufs, res, inst.n_missions)
+
+
+def solve_noalloc(inst: DeviceInstance, variant=AT_TABU, tenure=7, iters=500, aspiration=True,
+                  restart_seed=0, trace=True, schedule=SCHED_AUTO, n_groups=0, block=0, chunk=0,
+                  stream=None, out=None):
+    """One solve with the library's fixed workspace (at_solve_noalloc): the
+    library allocates nothing; the result buffers are the caller's (`out`, as
+    _alloc_result makes them, or allocated here)."""
+    pr = make_params(variant, tenure, iters, aspiration, restart_seed, trace, schedule, n_groups,
+                     block, chunk)
+    ci = inst.c_struct()
+    bufs = out if out is not None else _alloc_result(inst.n_missions, inst.n_vehicles, iters,
+                                                     trace, inst.travel.device)
+    res = _c_result(bufs)
+    _check(lib().at_solve_noalloc(C.byref(ci), C.byref(pr), _stream_ptr(stream), C.byref(res)))
     return _finish(bufs, res, inst.n_missions)
 
 

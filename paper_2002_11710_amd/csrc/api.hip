@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
@@ -616,7 +617,7 @@ struct EventPair {
 };
 
 static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, char *ws,
-                    const WsPlan &p, hipStream_t s, at_result *const *outs)
+                    const WsPlan &p, hipStream_t s, at_result *const *outs, bool timed)
 {
     const InstDev *dev_insts = (const InstDev *)(ws + p.insts);
     JobDev *dj = (JobDev *)(ws + p.jobs);
@@ -643,17 +644,19 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
     if ((e = fill_u32((uint32_t *)ds, 0u, sizeof(JobScal) * (size_t)n / 4, s)) != hipSuccess)
         return hip_fail(e, "clear results");
     EventPair ev;
-    if ((e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
-    if ((e = hipEventRecord(ev.a, s)) != hipSuccess) return hip_fail(e, "event record");
+    if (timed) {
+        if ((e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
+        if ((e = hipEventRecord(ev.a, s)) != hipSuccess) return hip_fail(e, "event record");
+    }
     rc = launch_jobs(jobs, order, dj, xs, s);
     if (rc) return rc;
-    if ((e = hipEventRecord(ev.b, s)) != hipSuccess) return hip_fail(e, "event record");
+    if (timed && (e = hipEventRecord(ev.b, s)) != hipSuccess) return hip_fail(e, "event record");
     std::vector<JobScal> hs((size_t)n);
     if ((e = hipMemcpyAsync(hs.data(), ds, sizeof(JobScal) * (size_t)n, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "read back results");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
     float ms = 0.f;
-    if ((e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess) return hip_fail(e, "event time");
+    if (timed && (e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess) return hip_fail(e, "event time");
     rc = AT_OK;
     for (int k = 0; k < n; ++k) {
         at_result *o = outs[k];
@@ -671,7 +674,7 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
 
 static int solve_common(int32_t n_inst, const at_instance *insts, const at_params *params,
                         int32_t n_restarts, void *ws, size_t ws_bytes, void *stream, at_result *out,
-                        bool single)
+                        bool single, bool timed = true)
 {
     for (int32_t i = 0; i < n_inst; ++i) {
         int rc = check_scalars(&insts[i], &params[i]);
@@ -708,7 +711,37 @@ static int solve_common(int32_t n_inst, const at_instance *insts, const at_param
         if (nj > 1 && h.pr.schedule == AT_SCHED_MULTI) h.pr.schedule = AT_SCHED_AUTO;
         outs[(size_t)k] = &out[k];
     }
-    return run_jobs(jobs, ih, base, p, s, outs.data());
+    return run_jobs(jobs, ih, base, p, s, outs.data(), timed);
+}
+
+// ---------------------------------------------------------------------------
+// at_solve_noalloc: at_solve with its workspace in a fixed device array
+// ---------------------------------------------------------------------------
+// The workspace of the allocation-free entry point: one array per device, held
+// until the process ends.  Host code never passes its name to a kernel (the
+// name is a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device.  Calls on one device are serialised by that device's lock.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu[kMaxDevices];
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address of device `dev`, the current device (looked up on its
+// first use; the caller holds that device's lock).
+static int scratch_address(int dev, void **ptr)
+{
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch: symbol address");
+        if (!p) return fail(AT_EDEVICE, "scratch: null symbol address");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return AT_OK;
 }
 
 }  // namespace at
@@ -765,6 +798,25 @@ int at_solve(const at_instance *inst, const at_params *params, void *ws, size_t 
 {
     if (!inst || !params || !out) return fail(AT_EINVAL, "null argument");
     return solve_common(1, inst, params, 1, ws, ws_bytes, stream, out, true);
+}
+
+int at_solve_noalloc(const at_instance *inst, const at_params *params, void *stream, at_result *out)
+{
+    if (!inst || !params || !out) return fail(AT_EINVAL, "null argument");
+    int rc = check_scalars(inst, params);
+    if (rc) return rc;
+    const size_t need = plan_ws(1, inst, params, 1).end;
+    if (need > kScratchBytes)
+        return fail(AT_ENOMEM, "at_solve_noalloc: this solve needs %zu bytes of workspace, the fixed array "
+                               "holds %zu (use at_solve with a caller workspace)", need, kScratchBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(AT_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    void *ws = nullptr;
+    if ((rc = scratch_address(dev, &ws)) != AT_OK) return rc;
+    return solve_common(1, inst, params, 1, ws, kScratchBytes, stream, out, true, false);
 }
 
 int at_debug_eval_moves(const at_instance *inst, const at_params *params, const int32_t *route_off,
