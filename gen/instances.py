@@ -74,6 +74,16 @@ class Instance:
     tenure: int = 7
     iters: int = 500
     meta: dict = field(default_factory=dict)
+    # the constrained model (None: unconstrained): per-mission time limit at the
+    # delivery point (s) and helicopter-only flag, per-vehicle type (0
+    # helicopter, 1 plane), the two speeds, flight limit and horizon (s)
+    deadline: np.ndarray | None = None
+    heli_only: np.ndarray | None = None
+    vehicle_type: np.ndarray | None = None
+    speed_heli: float = SPEED_KMH
+    speed_plane: float = SPEED_KMH
+    flight_limit: int = 0
+    horizon: int = 0
 
     @property
     def n_locs(self) -> int:
@@ -208,4 +218,80 @@ def poisson_arrivals(n: int, lam: float, stream_seed: int) -> np.ndarray:
     for i in range(n):
         t += -math.log(1.0 - rng.u01()) / lam
         out[i] = t
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The constrained model of the paper (Section 3)
+# ---------------------------------------------------------------------------
+HELI_KMH, PLANE_KMH = 300.0, 500.0        # rotary-wing and fixed-wing speeds
+FLIGHT_LIMIT_S, HORIZON_S = 10 * 3600, 24 * 3600
+
+
+FLEET_LAT_SPAN, FLEET_LON_SPAN = 4.0, 6.0   # the constrained workloads' region: 47-51 N, 91-85 W
+
+
+def fleet_instance(seed: int, n_missions: int, n_fac: int = 40, n_plane: int = 4,
+                   n_heli: int = 8, w_lo: int = 1 * 3600, w_hi: int = 23 * 3600,
+                   heli_share: int = 4, tenure: int = 5, iters: int = 300) -> Instance:
+    """An instance of the constrained model, drawn from SplitMix64(seed).
+
+    As the paper's evaluation: one vehicle per base, the first n_plane bases
+    hold planes (500 km/h), the other n_heli helicopters (300 km/h); a flight
+    limit of 10 h and a 24 h horizon.  Points lie in a regional box of 4 x 6
+    degrees (47-51 N, 91-85 W: a region one fleet serves in a day; the
+    unconstrained workloads' larger box leaves most missions unreachable within
+    these limits).  Draw order: F facilities and B bases (lat then lon each),
+    M missions by rejection (as make_instance), then each mission's time limit
+    at its delivery point, w = w_lo + randint(w_hi - w_lo + 1) seconds, then
+    each mission's helicopter-only flag, randint(heli_share) == 0.
+    """
+    n_bases = n_plane + n_heli
+    if n_fac < 2 or n_missions < 0 or n_missions > n_fac * (n_fac - 1):
+        raise ValueError("need F >= 2 and at most F(F-1) missions")
+    rng = SplitMix64(seed)
+    n_locs = n_fac + n_bases
+    lat = np.empty(n_locs, dtype=np.float64)
+    lon = np.empty(n_locs, dtype=np.float64)
+    for i in range(n_locs):
+        lat[i] = 47.0 + FLEET_LAT_SPAN * rng.u01()
+        lon[i] = -91.0 + FLEET_LON_SPAN * rng.u01()
+    used = set()
+    pick = np.empty(n_missions, dtype=np.int32)
+    dlv = np.empty(n_missions, dtype=np.int32)
+    for m in range(n_missions):
+        while True:
+            p = rng.randint(n_fac)
+            d = rng.randint(n_fac)
+            if p != d and (p, d) not in used:
+                break
+        used.add((p, d))
+        pick[m] = p
+        dlv[m] = d
+    base = Instance(lat, lon, pick, dlv, np.zeros(0, dtype=np.int32), n_fac, n_bases, seed, tenure,
+                    iters)
+    w = np.array([w_lo + rng.randint(w_hi - w_lo + 1) for _ in range(n_missions)], dtype=np.int32)
+    heli = np.array([1 if rng.randint(heli_share) == 0 else 0 for _ in range(n_missions)],
+                    dtype=np.int32)
+    base.vehicle_loc = np.array([n_fac + v for v in range(n_bases)], dtype=np.int32)
+    base.vehicle_type = np.array([1 if v < n_plane else 0 for v in range(n_bases)], dtype=np.int32)
+    base.deadline = w
+    base.heli_only = heli
+    base.speed_heli, base.speed_plane = HELI_KMH, PLANE_KMH
+    base.flight_limit, base.horizon = FLIGHT_LIMIT_S, HORIZON_S
+    return base
+
+
+def fleet_specs(n: int, stream_seed: int = 3):
+    """The paper-scale batch: per instance from SplitMix64(stream_seed),
+    M = 12 + 3 * randint(8) (the paper's 12, 15, ..., 33 missions), 40
+    facilities, 4 plane and 8 helicopter bases, tenure 5 + randint(5),
+    inst_seed = next()."""
+    rng = SplitMix64(stream_seed)
+    out = []
+    for k in range(n):
+        m = 12 + 3 * rng.randint(8)
+        ten = 5 + rng.randint(5)
+        s = rng.next()
+        out.append(dict(index=k, n_missions=m, tenure=ten, seed=s))
     return out

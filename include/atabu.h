@@ -46,6 +46,7 @@ extern "C" {
 #define AT_ENOMEM (-3)   /* workspace too small, or a request over the memory budget */
 #define AT_EAGAIN (-4)   /* result not ready yet (serving) */
 #define AT_EDEVICE (-5)  /* a HIP error or a device-side failure */
+#define AT_EINFEAS (-6)  /* Algorithm 1 found no feasible start (constrained model) */
 
 #define AT_TABU 0        /* Tabu search (Algorithm 3) */
 #define AT_NS 1          /* neighbourhood search (Algorithm 2): stops at a local optimum */
@@ -55,6 +56,14 @@ extern "C" {
 #define AT_SCHED_WG 1    /* one workgroup per solve, the whole state in LDS */
 #define AT_SCHED_MULTI 2 /* several workgroups per solve, state replicated in each one's LDS */
 #define AT_SCHED_GLOBAL 3 /* several workgroups per solve, state in HBM (large instances) */
+#define AT_SCHED_WAVE 4  /* one wavefront per solve, the whole state in LDS (small instances,
+                            the constrained model and the sweep form) */
+
+/* Forms of the search (at_params.form). */
+#define AT_FORM_BEST 0   /* every iteration scores the whole neighbourhood and applies the best */
+#define AT_FORM_SWEEP 1  /* Algorithms 2 and 3 as printed: bases in turn, each base's missions in
+                            turn, each mission moved to its best strictly better place in
+                            another base (WAVE schedule only) */
 
 /* One instance.  Locations are numbered 0..n_locs-1; the travel matrix gives
  * integer seconds, travel[i*n_locs + j] = time from location i to location j
@@ -62,7 +71,25 @@ extern "C" {
  * pickup[m] to delivery[m]; vehicle v starts and ends at vehicle_loc[v].
  * Limits: 1 <= n_locs <= 65535, 0 <= n_missions <= 65535, 1 <= n_vehicles
  * <= 65535, pickup != delivery, every travel time in [0, 2^23), and
- * M*(M+V) + M*(M-1)/2 < 2^32. */
+ * M*(M+V) + M*(M-1)/2 < 2^32.
+ *
+ * The constrained model of Section 3 (Eqs (7)-(10)) is switched on field by
+ * field (all NULL / 0: the unconstrained model, every move feasible):
+ *   travel_plane, vehicle_type: a second matrix for planes (Eq (1) at the
+ *     plane speed) and each vehicle's type (0 helicopter: `travel`; 1 plane:
+ *     `travel_plane`); each route's flights, loaded legs included, are timed
+ *     in its vehicle's matrix (Eq (2) with l = b_k);
+ *   deadline: the time (seconds from the start, >= 0) by which mission m's
+ *     vehicle must reach its delivery point; the vehicle then waits there
+ *     until that time before it flies on (Eqs (8)-(9)); every vehicle leaves
+ *     its base at 0 and must be back by `horizon`;
+ *   heli_only: 1 for a mission only a helicopter may fly (Eq (10));
+ *   flight_limit > 0: a route's flight time, waiting excluded, is at most
+ *     this (Eq (7)).
+ * A move whose result breaks a constraint is not a move.  The constrained
+ * model runs on the WAVE schedule only, with at most 1024 missions and 256
+ * vehicles, and its greedy start is Algorithm 1 with its checks (see
+ * at_params); a solve without a feasible start ends with status AT_EINFEAS. */
 typedef struct at_instance {
     int32_t n_locs;
     const int32_t *travel;       /* device, n_locs*n_locs, row-major */
@@ -71,6 +98,12 @@ typedef struct at_instance {
     const int32_t *delivery;     /* device, n_missions */
     int32_t n_vehicles;
     const int32_t *vehicle_loc;  /* device, n_vehicles */
+    const int32_t *travel_plane; /* device, n_locs*n_locs, or NULL (one matrix) */
+    const int32_t *vehicle_type; /* device, n_vehicles (0 or 1), or NULL (all 0) */
+    const int32_t *deadline;     /* device, n_missions, or NULL (no time limits) */
+    const int32_t *heli_only;    /* device, n_missions (0 or 1), or NULL (none) */
+    int32_t flight_limit;        /* seconds of flight per vehicle; <= 0: no limit */
+    int32_t horizon;             /* seconds; used with deadline (> 0) */
 } at_instance;
 
 typedef struct at_params {
@@ -87,8 +120,29 @@ typedef struct at_params {
                                HBM-resident schedule uses at most 512) */
     int32_t chunk;          /* partner positions per swap work unit: 0 = auto, else 8, 16,
                                32 or 64 (relocate units take twice as many gaps, at most 64) */
-    int32_t reserved;
+    int32_t form;           /* AT_FORM_BEST or AT_FORM_SWEEP */
 } at_params;
+
+/* The sweep form (AT_FORM_SWEEP), Algorithm 2 (AT_NS) or 3 (AT_TABU) as
+ * printed: passes over the vehicles, each vehicle's missions (those on it
+ * when its turn begins) in turn; each mission moves to the gap of another
+ * vehicle with the smallest cost change if that change is negative (the
+ * first such gap in vehicle then position order on ties; compatible,
+ * feasible, and for Tabu not listed); Tabu lists (mission, vehicle left) for
+ * tenure - 1 further turns.  Passes end when one moves nothing or after
+ * max_iters turns.  With restart_seed != 0 the vehicle order of every pass and
+ * the mission order of every vehicle's turn are Fisher-Yates orders drawn in
+ * that sequence from SplitMix64(restart_seed).  Results: one trace record per
+ * turn (the relocate slot index, or 0xFFFFFFFF when the mission stays; flags
+ * 0); the best solution is the final one; iters_done = turns run; best_iter =
+ * the last turn that moved a mission.
+ *
+ * The greedy start of the constrained model (Algorithm 1): helicopter-only
+ * missions first, then the others, each group by deadline (ties: mission id,
+ * or rank in the SplitMix64(restart_seed) Fisher-Yates order); each mission is
+ * appended to the vehicle where it fits at the least added flight time (ties:
+ * lowest vehicle); where it fits nowhere, one Algorithm 2 sweep over the
+ * missions placed so far, then one more try, then AT_EINFEAS. */
 
 /* Results of one solve.  Arrays are device memory supplied by the caller;
  * scalars are written by the library (host).  The routes are the best

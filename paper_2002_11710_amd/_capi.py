@@ -7,9 +7,10 @@ import threading
 
 import numpy as np
 
-AT_OK, AT_EINVAL, AT_ERANGE, AT_ENOMEM, AT_EAGAIN, AT_EDEVICE = 0, -1, -2, -3, -4, -5
+AT_OK, AT_EINVAL, AT_ERANGE, AT_ENOMEM, AT_EAGAIN, AT_EDEVICE, AT_EINFEAS = 0, -1, -2, -3, -4, -5, -6
 AT_TABU, AT_NS = 0, 1
-SCHED_AUTO, SCHED_WG, SCHED_MULTI, SCHED_GLOBAL = 0, 1, 2, 3
+SCHED_AUTO, SCHED_WG, SCHED_MULTI, SCHED_GLOBAL, SCHED_WAVE = 0, 1, 2, 3, 4
+FORM_BEST, FORM_SWEEP = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libatabu.so")
@@ -29,14 +30,16 @@ class AtError(RuntimeError):
 class _Instance(C.Structure):
     _fields_ = [("n_locs", C.c_int32), ("travel", C.c_void_p), ("n_missions", C.c_int32),
                 ("pickup", C.c_void_p), ("delivery", C.c_void_p), ("n_vehicles", C.c_int32),
-                ("vehicle_loc", C.c_void_p)]
+                ("vehicle_loc", C.c_void_p), ("travel_plane", C.c_void_p),
+                ("vehicle_type", C.c_void_p), ("deadline", C.c_void_p), ("heli_only", C.c_void_p),
+                ("flight_limit", C.c_int32), ("horizon", C.c_int32)]
 
 
 class _Params(C.Structure):
     _fields_ = [("variant", C.c_int32), ("tenure", C.c_int32), ("max_iters", C.c_int32),
                 ("aspiration", C.c_int32), ("restart_seed", C.c_uint64), ("trace", C.c_int32),
                 ("schedule", C.c_int32), ("n_groups", C.c_int32), ("block", C.c_int32),
-                ("chunk", C.c_int32), ("reserved", C.c_int32)]
+                ("chunk", C.c_int32), ("form", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -149,14 +152,29 @@ def build_travel_device(lat, lon, speed_kmh: float = 260.0, stream=None):
 
 
 class DeviceInstance:
-    """An instance resident in HBM: travel matrix, missions, vehicle bases."""
+    """An instance resident in HBM: travel matrix, missions, vehicle bases, and
+    optionally the constrained model's fields (see at_instance in atabu.h):
+    a plane travel matrix with each vehicle's type, each mission's time limit at
+    its delivery point (with the horizon), helicopter-only flags and the flight
+    limit."""
 
-    def __init__(self, travel, pickup, delivery, vehicle_loc):
+    def __init__(self, travel, pickup, delivery, vehicle_loc, travel_plane=None,
+                 vehicle_type=None, deadline=None, heli_only=None, flight_limit=0, horizon=0):
         torch = _torch()
-        self.travel = torch.as_tensor(travel, dtype=torch.int32).contiguous().cuda()
-        self.pickup = torch.as_tensor(pickup, dtype=torch.int32).contiguous().cuda()
-        self.delivery = torch.as_tensor(delivery, dtype=torch.int32).contiguous().cuda()
-        self.vehicle_loc = torch.as_tensor(vehicle_loc, dtype=torch.int32).contiguous().cuda()
+
+        def dev(x):
+            return None if x is None else torch.as_tensor(x, dtype=torch.int32).contiguous().cuda()
+
+        self.travel = dev(travel)
+        self.pickup = dev(pickup)
+        self.delivery = dev(delivery)
+        self.vehicle_loc = dev(vehicle_loc)
+        self.travel_plane = dev(travel_plane)
+        self.vehicle_type = dev(vehicle_type)
+        self.deadline = dev(deadline)
+        self.heli_only = dev(heli_only)
+        self.flight_limit = int(flight_limit)
+        self.horizon = int(horizon)
         self.n_locs = int(self.travel.shape[0])
         self.n_missions = int(self.pickup.shape[0])
         self.n_vehicles = int(self.vehicle_loc.shape[0])
@@ -173,17 +191,19 @@ class DeviceInstance:
                                speed_kmh)
 
     def c_struct(self) -> _Instance:
+        def p(t):
+            return t.data_ptr() if t is not None and t.numel() else None
         return _Instance(self.n_locs, self.travel.data_ptr(), self.n_missions,
-                         self.pickup.data_ptr() if self.n_missions else None,
-                         self.delivery.data_ptr() if self.n_missions else None,
-                         self.n_vehicles, self.vehicle_loc.data_ptr())
+                         p(self.pickup), p(self.delivery), self.n_vehicles,
+                         self.vehicle_loc.data_ptr(), p(self.travel_plane), p(self.vehicle_type),
+                         p(self.deadline), p(self.heli_only), self.flight_limit, self.horizon)
 
 
 def make_params(variant=AT_TABU, tenure=7, iters=500, aspiration=True, restart_seed=0, trace=True,
-                schedule=SCHED_AUTO, n_groups=0, block=0, chunk=0) -> _Params:
+                schedule=SCHED_AUTO, n_groups=0, block=0, chunk=0, form=FORM_BEST) -> _Params:
     return _Params(int(variant), int(tenure), int(iters), 1 if aspiration else 0,
                    C.c_uint64(int(restart_seed) & ((1 << 64) - 1)), 1 if trace else 0,
-                   int(schedule), int(n_groups), int(block), int(chunk), 0)
+                   int(schedule), int(n_groups), int(block), int(chunk), int(form))
 
 
 def _alloc_result(M: int, V: int, iters: int, trace: bool, device):
@@ -244,10 +264,10 @@ def _workspace(nbytes: int, ws=None):
 
 def solve(inst: DeviceInstance, variant=AT_TABU, tenure=7, iters=500, aspiration=True,
           restart_seed=0, trace=True, schedule=SCHED_AUTO, n_groups=0, block=0, chunk=0,
-          ws=None, stream=None, out=None):
+          form=FORM_BEST, ws=None, stream=None, out=None):
     """One solve (at_solve).  Returns device tensors and host scalars."""
     pr = make_params(variant, tenure, iters, aspiration, restart_seed, trace, schedule, n_groups,
-                     block, chunk)
+                     block, chunk, form)
     ci = inst.c_struct()
     nbytes = int(lib().at_workspace_size(1, C.byref(ci), C.byref(pr), 1))
     if nbytes == 0:
@@ -277,11 +297,14 @@ def solve_noalloc(inst: DeviceInstance, variant=AT_TABU, tenure=7, iters=500, as
     return _finish(bufs, res, inst.n_missions)
 
 
-def solve_batch(insts, params, n_restarts=1, ws=None, stream=None, outs=None):
+def solve_batch(insts, params, n_restarts=1, ws=None, stream=None, outs=None,
+                allow_infeasible=False):
     """n instances x n_restarts solves in one call (at_solve_batch).
 
     params: one _Params (make_params) per instance.  Returns a list in
-    (instance, restart) order."""
+    (instance, restart) order.  With allow_infeasible, a call whose only
+    failures are starts Algorithm 1 could not build (AT_EINFEAS) returns the
+    results, each with its own status."""
     n = len(insts)
     ia = (_Instance * n)(*[i.c_struct() for i in insts])
     pa = (_Params * n)(*params)
@@ -296,18 +319,21 @@ def solve_batch(insts, params, n_restarts=1, ws=None, stream=None, outs=None):
                 outs.append(_alloc_result(inst.n_missions, inst.n_vehicles, params[i].max_iters,
                                           bool(params[i].trace), inst.travel.device))
     ra = (_Result * len(outs))(*[_c_result(b) for b in outs])
-    _check(lib().at_solve_batch(n, ia, pa, n_restarts, _dptr(ws), ws.numel(), _stream_ptr(stream),
-                                ra))
+    rc = lib().at_solve_batch(n, ia, pa, n_restarts, _dptr(ws), ws.numel(), _stream_ptr(stream), ra)
+    if not (allow_infeasible and rc == AT_EINFEAS):
+        _check(rc)
     return [_finish(outs[k], ra[k], insts[k // n_restarts].n_missions) for k in range(len(outs))]
 
 
 def debug_eval_moves(inst: DeviceInstance, route_off, route_seq, tabu_until, t, cur, best,
-                     variant=AT_TABU, aspiration=True, chunk=0, block=0, ws=None, stream=None):
-    """Every slot's 64-bit key for a state, as the search kernels compute it (uint64 numpy)."""
+                     variant=AT_TABU, aspiration=True, chunk=0, block=0, schedule=SCHED_AUTO,
+                     ws=None, stream=None):
+    """Every slot's 64-bit key for a state, as the search kernels compute it (uint64 numpy);
+    schedule SCHED_WAVE (or a constrained instance) dumps the wave schedule's evaluation."""
     torch = _torch()
     M, V = inst.n_missions, inst.n_vehicles
     n = M * (M + V) + M * (M - 1) // 2
-    pr = make_params(variant, 0, 0, aspiration, 0, False, SCHED_AUTO, 0, block, chunk)
+    pr = make_params(variant, 0, 0, aspiration, 0, False, schedule, 0, block, chunk)
     ci = inst.c_struct()
     nbytes = int(lib().at_workspace_size(1, C.byref(ci), C.byref(pr), 1))
     ws = _workspace(nbytes, ws)

@@ -65,8 +65,21 @@ int check_scalars(const at_instance *in, const at_params *pr)
         return fail(AT_EINVAL, "block must be 0, 256, 512 or 1024");
     if (pr->chunk != 0 && (pr->chunk != 8 && pr->chunk != 16 && pr->chunk != 32 && pr->chunk != 64))
         return fail(AT_EINVAL, "chunk must be 0, 8, 16, 32 or 64");
-    if (pr->schedule < AT_SCHED_AUTO || pr->schedule > AT_SCHED_GLOBAL) return fail(AT_EINVAL, "bad schedule");
+    if (pr->schedule < AT_SCHED_AUTO || pr->schedule > AT_SCHED_WAVE) return fail(AT_EINVAL, "bad schedule");
     if (pr->n_groups < 0 || pr->n_groups > 4096) return fail(AT_EINVAL, "n_groups outside [0, 4096]");
+    if (pr->form != AT_FORM_BEST && pr->form != AT_FORM_SWEEP) return fail(AT_EINVAL, "bad form %d", pr->form);
+    const bool cons = in->travel_plane || in->vehicle_type || in->deadline || in->heli_only || in->flight_limit > 0;
+    if (cons || pr->form == AT_FORM_SWEEP || pr->schedule == AT_SCHED_WAVE) {
+        if (pr->schedule != AT_SCHED_AUTO && pr->schedule != AT_SCHED_WAVE)
+            return fail(AT_EINVAL, "the constrained model and the sweep form run on the wave schedule only");
+        if (in->n_missions > kWaveMaxMissions || in->n_vehicles > kWaveMaxVehicles)
+            return fail(AT_EINVAL, "the wave schedule takes at most %d missions and %d vehicles",
+                        kWaveMaxMissions, kWaveMaxVehicles);
+    }
+    if (in->deadline && (in->horizon <= 0 || in->horizon > (1 << 29)))
+        return fail(AT_EINVAL, "horizon %d outside (0, 2^29]", in->horizon);
+    if (in->vehicle_type && !in->travel_plane)
+        return fail(AT_EINVAL, "vehicle types need the plane travel matrix");
     return AT_OK;
 }
 
@@ -127,6 +140,12 @@ void carve_inst(InstDev &d, const at_instance &in, char *base, bool with_t)
     d.tct = with_t ? (void *)(base + o) : nullptr;
     d.tcr = with_t ? (void *)(base + o + al256((size_t)d.tc_cap)) : nullptr;
     d.status = AT_EDEVICE;
+    d.T2 = in.travel_plane;
+    d.vtype = in.vehicle_type;
+    d.w = in.deadline;
+    d.heli = in.heli_only;
+    d.flimit = in.flight_limit > 0 ? in.flight_limit : 0;
+    d.horizon = in.deadline ? in.horizon : 0;
 }
 
 void carve_gstate(GlobalBufs &g, int M, int V, int n_ring, char *base)
@@ -257,6 +276,15 @@ static int pick_block(const at_params &pr, int64_t slots)
     return 1024;
 }
 
+// Whether the tuned table gives solves of this many move slots to the wave
+// schedule.
+static bool pick_wave(int64_t slots)
+{
+    for (const TunedRow &r : kTuned)
+        if (slots < r.max_slots) return r.wave != 0;
+    return false;
+}
+
 static int pick_chunk(const at_params &pr, int64_t slots)
 {
     if (pr.chunk) return pr.chunk;
@@ -277,9 +305,30 @@ static void set_block_size(JobHost &h)
     h.lds = global_lds_bytes(h.gk, h.dR, h.dC, h.dM, h.dV, h.desz, h.tb16 ? 2 : 4);
 }
 
+// Wave schedule: one wavefront per solve (the constrained model, the sweep
+// form, or a small unconstrained solve the tuned table gives to it).
+static int plan_wave(JobHost &h, const InstDev &d)
+{
+    const bool two = d.T2 != nullptr;
+    const int esz = constrained(d) ? 4 : d.esz;
+    h.kind = AT_SCHED_WAVE;
+    h.esz16 = esz == 2 ? 1 : 0;
+    h.tb16 = 0;
+    h.lds = wave_lds_bytes(d.M, d.V, d.R, d.Cs, esz, two);
+    h.groups = 1;
+    h.block = kWave;
+    if (h.lds > kLdsLimit)
+        return fail(AT_ENOMEM, "instance too large for the wave schedule (%u bytes of LDS per solve)", h.lds);
+    return AT_OK;
+}
+
 int plan_job(JobHost &h, const InstDev &d, bool alone)
 {
     h.slots = n_slots(d.M, d.V);
+    if (constrained(d) || h.pr.form == AT_FORM_SWEEP || h.pr.schedule == AT_SCHED_WAVE) {
+        if (h.chunked) return fail(AT_EINVAL, "served requests run the best form on the unconstrained model");
+        return plan_wave(h, d);
+    }
     h.tb16 = tabu_bytes(h.pr) == 2 ? 1 : 0;
     h.esz16 = d.esz == 2 ? 1 : 0;
     h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
@@ -312,6 +361,9 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
         return AT_OK;
     }
     h.kind = AT_SCHED_WG;
+    if (!h.chunked && h.pr.schedule == AT_SCHED_AUTO && pick_wave(h.slots) &&
+        wave_lds_bytes(d.M, d.V, d.R, d.Cs, d.esz, false) <= kLdsLimit / 2)
+        return plan_wave(h, d);
     if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
         // measured on gfx950 (16 x 400 missions): 512 threads, 8-column swap units
         // (16-column relocate units), one wavefront per work unit (the iteration
@@ -366,6 +418,7 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.scal = scal;
     j.st = nullptr;
     j.gb = h.gstate;
+    j.form = h.pr.form;
     j.gk = h.gk;
     j.g0 = h.g0;
     j.ng = h.groups;
@@ -429,15 +482,16 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
 {
     hipError_t e;
     const int n = (int)order.size();
-    struct Cls { int k0, k1, block, tb16, esz16; uint32_t lds; };
+    struct Cls { int k0, k1, kind, block, tb16, esz16; uint32_t lds; };
     std::vector<Cls> cls;
     int k = 0;
-    while (k < n && jobs[(size_t)order[(size_t)k]].kind == AT_SCHED_WG) {
+    auto one_per_solve = [](int kind) { return kind == AT_SCHED_WG || kind == AT_SCHED_WAVE; };
+    while (k < n && one_per_solve(jobs[(size_t)order[(size_t)k]].kind)) {
         const JobHost &hf = jobs[(size_t)order[(size_t)k]];
-        Cls c{k, k, hf.block, hf.tb16, hf.esz16, 0};
+        Cls c{k, k, hf.kind, hf.block, hf.tb16, hf.esz16, 0};
         while (c.k1 < n) {
             const JobHost &h = jobs[(size_t)order[(size_t)c.k1]];
-            if (h.kind != AT_SCHED_WG || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block) break;
+            if (h.kind != hf.kind || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block) break;
             c.lds = std::max(c.lds, h.lds);
             ++c.k1;
         }
@@ -464,12 +518,23 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
             }
             if (split && (e = hipStreamWaitEvent(st, fork, 0)) != hipSuccess) { rc = hip_fail(e, "fork"); break; }
             const int count = q.k1 - q.k0;
-            const int by_lds = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(q.lds, 1)));
-            const int by_waves = std::max(1, 16 * kWave / q.block);
-            const int per_cu = std::min(by_lds, by_waves);
-            const int grid = std::max(1, std::min(count, num_cus() * per_cu));
-            if ((e = launch_search_wg(dj + q.k0, count, &xs->queues[c], grid, q.block, q.lds, q.tb16,
-                                      q.esz16, st)) != hipSuccess) {
+            if (q.kind == AT_SCHED_WAVE) {
+                // up to four solves (wavefronts) per workgroup, as many workgroups per CU as
+                // LDS holds
+                const uint32_t per = std::max<uint32_t>(q.lds, 16);
+                const int wpg = (int)std::max<uint32_t>(1, std::min<uint32_t>(4, kLdsLimit / per));
+                const int by_lds = std::max(1, (int)((kLdsLimit + 64) / (per * (uint32_t)wpg)));
+                const int per_cu = std::min(by_lds, 16 / wpg);
+                const int grid = std::max(1, std::min((count + wpg - 1) / wpg, num_cus() * per_cu));
+                e = launch_search_wave(dj + q.k0, count, &xs->queues[c], grid, wpg, per, q.esz16, st);
+            } else {
+                const int by_lds = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(q.lds, 1)));
+                const int by_waves = std::max(1, 16 * kWave / q.block);
+                const int per_cu = std::min(by_lds, by_waves);
+                const int grid = std::max(1, std::min(count, num_cus() * per_cu));
+                e = launch_search_wg(dj + q.k0, count, &xs->queues[c], grid, q.block, q.lds, q.tb16, q.esz16, st);
+            }
+            if (e != hipSuccess) {
                 rc = hip_fail(e, "search launch");
                 break;
             }
@@ -523,9 +588,11 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
     for (int k = 0; k < n; ++k) order[(size_t)k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const JobHost &x = jobs[(size_t)a], &y = jobs[(size_t)b];
-        const int cx = x.kind == AT_SCHED_WG ? 0 : x.kind, cy = y.kind == AT_SCHED_WG ? 0 : y.kind;
+        // one-solve-per-group kinds first (wave, then workgroup), then the cooperative ones
+        auto grp = [](int kind) { return kind == AT_SCHED_WAVE ? 0 : kind == AT_SCHED_WG ? 1 : kind; };
+        const int cx = grp(x.kind), cy = grp(y.kind);
         if (cx != cy) return cx < cy;
-        if (x.kind == AT_SCHED_WG || x.kind == AT_SCHED_GLOBAL) {
+        if (x.kind == AT_SCHED_WG || x.kind == AT_SCHED_GLOBAL || x.kind == AT_SCHED_WAVE) {
             const int kx = (x.esz16 * 2 + x.tb16) * 4096 + x.block, ky = (y.esz16 * 2 + y.tb16) * 4096 + y.block;
             if (kx != ky) return kx > ky;
         }
@@ -666,7 +733,11 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
         o->iters_done = hs[(size_t)k].iters_done;
         o->best_iter = hs[(size_t)k].best_iter;
         o->status = hs[(size_t)k].status;
-        if (o->status != AT_OK && rc == AT_OK)
+        if (o->status == AT_EINFEAS && rc == AT_OK)
+            rc = fail(AT_EINFEAS, "solve %d: Algorithm 1 found no feasible start", k);
+        else if ((o->status == AT_EINVAL || o->status == AT_ERANGE) && rc == AT_OK)
+            rc = fail(o->status, "solve %d: a constrained-model input is out of range", k);
+        else if (o->status != AT_OK && rc == AT_OK)
             rc = fail(AT_EDEVICE, "solve %d failed on the device (status %d)", k, o->status);
     }
     return rc;
@@ -837,7 +908,9 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     rc = prepare_instances(1, (InstDev *)(base + p.insts), ih, s);
     if (rc) return rc;
     const InstDev &d = ih[0];
-    const uint32_t lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, 4).total;
+    const bool wave = constrained(d) || params->schedule == AT_SCHED_WAVE;
+    const uint32_t lds = wave ? wave_lds_bytes(d.M, d.V, d.R, d.Cs, constrained(d) ? 4 : d.esz, d.T2 != nullptr)
+                              : lds_layout(d.M, d.V, d.R, d.Cs, d.esz, 4).total;
     if (lds > kLdsLimit) return fail(AT_ENOMEM, "instance too large for the LDS-resident key dump");
     JobHost h;
     h.inst = 0;
@@ -859,9 +932,13 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params, const 
     hipError_t e = hipMemcpyAsync(dj, &j, sizeof(JobDev), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "upload job");
     const int block = params->block ? params->block : 256;
-    if ((e = launch_debug_keys(dj, route_off, route_seq, tabu_until, t, cur, best, keys_out, block,
-                               lds, d.esz == 2, s)) != hipSuccess)
-        return hip_fail(e, "key dump launch");
+    if (wave)
+        e = launch_debug_keys_wave(dj, route_off, route_seq, tabu_until, t, cur, best, keys_out, lds,
+                                   !constrained(d) && d.esz == 2, s);
+    else
+        e = launch_debug_keys(dj, route_off, route_seq, tabu_until, t, cur, best, keys_out, block, lds,
+                              d.esz == 2, s);
+    if (e != hipSuccess) return hip_fail(e, "key dump launch");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "key dump");
     return AT_OK;
 }

@@ -78,7 +78,16 @@ struct InstDev {
     int32_t Cg;                       // row stride of the aligned copy
     int32_t maxT;
     int64_t svc_sum;
+    // the constrained model (null / 0 when off; filled by the host)
+    const int32_t *T2, *vtype, *w, *heli;
+    int32_t flimit, horizon;          // flimit <= 0: no flight limit
 };
+
+// An instance uses the constrained model when any of its fields is set.
+__host__ __device__ inline bool constrained(const InstDev &d)
+{
+    return d.T2 || d.vtype || d.w || d.heli || d.flimit > 0;
+}
 
 struct JobScal {
     int64_t best_obj, final_obj;
@@ -128,6 +137,7 @@ struct JobDev {
     int32_t tb16;                     // tabu entries stored as uint16 in LDS
     int32_t chunk;                    // partner positions per swap work unit
     int32_t rchunk;                   // gaps per relocate work unit
+    int32_t form;                     // AT_FORM_BEST or AT_FORM_SWEEP (wave schedule)
     int32_t gk;                       // global schedule: missions staged per block
     int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
     uint64_t seed;
@@ -269,6 +279,15 @@ hipError_t launch_debug_keys(const JobDev *job, const int32_t *off, const int32_
                              uint64_t *keys, int block, uint32_t lds_bytes, int esz16,
                              hipStream_t s);
 int max_groups_multi(int block, uint32_t lds_bytes, int tb16, int esz16);
+// wave schedule: LDS bytes of one solve, launcher, key dump
+uint32_t wave_lds_bytes(int M, int V, int R, int Cs, int esz, bool two);
+constexpr int kWaveMaxMissions = 1024;
+constexpr int kWaveMaxVehicles = 256;
+hipError_t launch_search_wave(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid,
+                              int waves_per_group, uint32_t lds_per_solve, int esz16, hipStream_t s);
+hipError_t launch_debug_keys_wave(const JobDev *job, const int32_t *off, const int32_t *seq,
+                                  const int32_t *tabu_until, int32_t t, int64_t cur, int64_t best,
+                                  uint64_t *keys, uint32_t lds_bytes, int esz16, hipStream_t s);
 uint32_t max_lds_bytes();
 int num_cus();
 hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);

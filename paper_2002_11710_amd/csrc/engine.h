@@ -33,6 +33,7 @@ struct JobHost {
     int dM = 0, dV = 0, dR = 0, dC = 0, desz = 4;   // instance sizes (global schedule LDS plan)
     int g0 = 0, launch = 0;           // global schedule: first workgroup, launch index (assign_groups)
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
+    bool chunked = false;             // run in chunks of iterations (serving): no wave schedule
 };
 
 int fail(int code, const char *fmt, ...);

@@ -228,6 +228,7 @@ struct Server {
                 r.job.pr = r.pr;
                 r.job.pr.schedule = r.pr.schedule == AT_SCHED_MULTI ? AT_SCHED_AUTO : r.pr.schedule;
                 r.job.seed = r.pr.restart_seed;
+                r.job.chunked = true;
                 rc[k] = plan_job(r.job, r.host_inst, false);
             }
             if (rc[k] == AT_OK && r.job.kind == AT_SCHED_GLOBAL)
@@ -416,6 +417,9 @@ int at_server_submit(void *server, const at_instance *inst, const at_params *par
     if (!sv || !ticket) return fail(AT_EINVAL, "null argument");
     int rc = check_scalars(inst, params);
     if (rc) return rc;
+    if (inst->travel_plane || inst->vehicle_type || inst->deadline || inst->heli_only || inst->flight_limit > 0 ||
+        params->form != AT_FORM_BEST || params->schedule == AT_SCHED_WAVE)
+        return fail(AT_EINVAL, "served requests run the best form on the unconstrained model");
     Request *r = new Request();
     r->inst = *inst;
     r->pr = *params;
