@@ -267,3 +267,37 @@ def test_wave_rejections():
         assert e.value.code == at.AT_EINVAL
     finally:
         srv.close()
+
+
+def _nonmetric_dev(w_n):
+    import test_oracle_fleet as tf
+    F = tf._nonmetric(w_n)
+    dev = at.DeviceInstance(F.T0, F.p, F.d, F.b, travel_plane=F.T1, vehicle_type=F.type,
+                            deadline=F.w, heli_only=None, flight_limit=F.flight_limit,
+                            horizon=F.horizon)
+    return F, dev
+
+
+def test_nonmetric_removal_and_ties():
+    """Hand-built non-metric instance: a mission whose removal would make its
+    route late stays (keys and sweep); three vehicles on one base give tied
+    sweep candidates, resolved to the first vehicle as in the oracle."""
+    off, seq = [0, 3, 5], [0, 1, 2, 3, 4]
+    for w_n in (600, 6000):
+        F, dev = _nonmetric_dev(w_n)
+        cur = F.feasible(off, seq)[1]
+        tabu = np.full((5, 2), -1, np.int32)
+        want = F.keys(off, seq, tabu, 0, cur, cur)
+        got, fast = at.debug_eval_moves(dev, off, seq, tabu, 0, cur, cur)
+        assert np.array_equal(got, want) and fast == int(want.min())
+        _same_sweep(F.sweep(variant=oracle.NS), at.solve(dev, variant=at.AT_NS, iters=1000,
+                                                         form=at.FORM_SWEEP), f"non-metric {w_n}")
+    for seed in range(4):
+        inst = make_instance(40 + seed, 30, 1, 3, 14)
+        P = oracle.Problem.from_instance(inst)
+        F = oracle.FleetProblem.relaxed(P.T, P.p, P.d, P.b)
+        dev = at.DeviceInstance.from_instance(inst)
+        for rs in (0, 5):
+            _same_sweep(F.sweep(variant=oracle.NS, restart_seed=rs),
+                        at.solve(dev, variant=at.AT_NS, iters=100000, restart_seed=rs, form=at.FORM_SWEEP),
+                        f"one-base sweep {seed} {rs}")

@@ -294,6 +294,7 @@ def _repair_cases():
 
 def test_greedy_repair_and_error_report():
     saved, failed = _repair_cases()
+    assert saved, "no instance the repair rescues"
     assert failed, "no instance where even the repaired greedy fails"
     for seed, F, stuck, off, seq, rep in saved:
         assert rep >= 1, seed
@@ -395,3 +396,73 @@ def test_sweep_relaxed_and_tenure_one():
         moves, turns = _sweep_by_hand(F, oracle.NS, 0, seed)
         assert turns == b["iters_done"]
         assert P.objective(b["best_off"], b["best_seq"]) == b["best_obj"]
+
+
+def test_sweep_ties_go_to_the_first_vehicle():
+    """Three vehicles on one base: a mission's moves into two empty routes cost
+    the same, and the sweep keeps the first (lower vehicle) of equal
+    candidates, as the Python driver does."""
+    n_tied = 0
+    for seed in range(6):
+        inst = make_instance(40 + seed, 30, 1, 3, 14)
+        P = oracle.Problem.from_instance(inst)
+        F = oracle.FleetProblem.relaxed(P.T, P.p, P.d, P.b)
+        for rs in (0, 5):
+            r = F.sweep(variant=oracle.NS, restart_seed=rs)
+            moves, turns = _sweep_by_hand(F, oracle.NS, 0, rs)
+            got = [(t, int(r["tr_move"][t]), int(r["tr_delta"][t])) for t in range(r["iters_done"])
+                   if r["tr_move"][t] != oracle.NO_MOVE]
+            assert got == moves and turns == r["iters_done"]
+            n_tied += len(moves)
+    assert n_tied > 0
+
+
+def _nonmetric(w_n):
+    """Vehicle 0 flies a, j, n; vehicle 1 flies c, e; the matrix breaks the
+    triangle inequality twice: a's delivery to n's pickup is slow (5000 s), so
+    taking j out makes n late unless its limit allows it; c's delivery to e's
+    pickup is slower still (9000 s), so putting j between c and e saves time."""
+    L = 11    # missions a, j, n, c, e fly 0->1, 2->3, 4->5, 6->7, 8->9; base 10
+    T = np.full((L, L), 50, dtype=np.int32)
+    np.fill_diagonal(T, 0)
+    T[1, 4] = 5000
+    T[7, 8] = 9000
+    T[5, 8] = 20000
+    p, d = [0, 2, 4, 6, 8], [1, 3, 5, 7, 9]
+    w = [200, 400, w_n, 290, 10000]
+    return oracle.FleetProblem(T, T, p, d, w, None, [10, 10], [0, 0], 10 ** 6, 10 ** 6)
+
+
+def test_taking_a_mission_out_must_leave_a_feasible_route():
+    off, seq = [0, 3, 5], [0, 1, 2, 3, 4]
+    tight, loose = _nonmetric(600), _nonmetric(6000)
+    for F in (tight, loose):
+        assert F.feasible(off, seq)[0]
+    # relocate j (mission 1) between c and e: G = off[1] + 1 + 1 = 5
+    slot = 1 * (5 + 2) + 5
+    no_tabu = np.full((5, 2), -1, np.int32)
+    for F, valid in ((tight, False), (loose, True)):
+        cur = F.feasible(off, seq)[1]
+        k0 = F.keys(off, seq, no_tabu, 0, cur, cur, mode=0)
+        k1 = F.keys(off, seq, no_tabu, 0, cur, cur, mode=1)
+        assert np.array_equal(k0, k1)
+        assert (k0[slot] != NONE) == valid
+        if valid:
+            assert int((int(k0[slot]) >> 32) & 0x7FFFFFFF) - (1 << 30) < 0
+
+
+def test_sweep_keeps_a_mission_whose_removal_breaks_its_route():
+    """Algorithm 1 builds exactly a, j, n | c, e on the non-metric instance;
+    the sweep's move of j between c and e saves 4000 s, but taking j out makes
+    n late under the tight limit: j stays there, and moves under the loose one."""
+    for w_n, moves_j in ((600, False), (6000, True)):
+        F = _nonmetric(w_n)
+        off, seq, rep = F.greedy(0)
+        assert list(off) == [0, 3, 5] and list(seq) == [0, 1, 2, 3, 4] and rep == 0
+        r = F.sweep(variant=oracle.NS)
+        assert (r["tr_move"][1] == 1 * 7 + 5) == moves_j
+        if moves_j:
+            assert r["tr_delta"][1] == -4000
+        moves, turns = _sweep_by_hand(F, oracle.NS, 0, 0)
+        assert [(t, int(r["tr_move"][t])) for t in range(turns) if r["tr_move"][t] != oracle.NO_MOVE] == \
+               [(t, m) for t, m, _ in moves]
