@@ -103,6 +103,10 @@ def parse():
     ap.add_argument("--stress", type=int, default=1000,
                     help="also run the 256 x 10000 stress instance for this many iterations "
                          "(Tabu and NS; 0: skip)")
+    ap.add_argument("--fleet", type=int, default=4096,
+                    help="also run this many paper-scale instances of the constrained model x 8 "
+                         "restarts (wave schedule; best form and sweep form; 0: skip)")
+    ap.add_argument("--no-lds-peak", action="store_true", help="skip the LDS bandwidth probe")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain per-instance comparisons (profiling runs)")
@@ -111,6 +115,38 @@ def parse():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--groups", type=int, default=0)
     return ap.parse_args()
+
+
+def lds_peak(strides=(1, 2, 4, 8, 16, 32, 64, 128)):
+    """Measured LDS read bandwidth (conflict-free ds_read_b32 over the whole GPU)
+    and the slowdown of each lane stride, from paper_2002_11710_amd/libldspeak.so."""
+    import ctypes as C
+
+    import torch
+    path = os.path.join(ROOT, "paper_2002_11710_amd", "libldspeak.so")
+    L = C.CDLL(path)
+    L.ldspeak_run.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                              C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = 2 * cus                      # two 64 KiB workgroups of 1024 threads per CU
+
+    def run(iters, stride):
+        ms, clk, wt = C.c_double(0), C.c_uint64(0), C.c_uint64(0)
+        rc = L.ldspeak_run(blocks, iters, stride, C.byref(ms), C.byref(clk), C.byref(wt))
+        if rc != 0:
+            raise RuntimeError(f"ldspeak_run: HIP error {rc}")
+        return ms.value, clk.value, wt.value
+
+    iters = 20000
+    ms, clk, wt = run(iters, 1)
+    nbytes = blocks * 1024 * iters * 16 * 4
+    ghz = clk / (wt / 100e6) / 1e9 if wt else None
+    out = {"bytes": nbytes, "ms": ms, "TBps": nbytes / (ms / 1000.0) / 1e12, "cus": cus,
+           "shader_GHz": ghz,
+           "B_per_clk_per_CU": (nbytes / (ms / 1000.0)) / (cus * ghz * 1e9) if ghz else None}
+    base = run(2000, 1)[0]
+    out["stride_slowdown"] = {str(s): run(2000, s)[0] / base for s in strides}
+    return out
 
 
 def host_cpu():
@@ -346,6 +382,14 @@ def main():
             lds.update(pmc_lds_busy_frac=k.get("lds_busy"), pmc_bank_conflict_frac=k.get("bank_conflict"),
                        pmc_valu_busy_frac=k.get("valu_busy"))
         line["lds_roofline"] = lds
+    if not args.no_lds_peak:
+        line["lds_peak"] = lds_peak()
+        if "lds_roofline" in line:
+            pk = line["lds_peak"]["TBps"] * 1e12
+            line["lds_roofline"].update(measured_peak_GBps=pk / 1e9,
+                                        frac_of_measured=line["batch"]["lds_bytes_per_s"] / pk)
+    if args.fleet:
+        line["fleet"] = bench_fleet(args.fleet, plain=not args.no_plain)
     if args.stress:
         line["stress"] = bench_stress(args.stress)
     if args.serve:
@@ -431,6 +475,70 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     out.update({"plain_sample_solves": n_plain, "plain_sample_s": t_plain,
                 "plain_solves_per_s": plain_sps,
                 "speedup_vs_plain": (n_inst * restarts / wall) / plain_sps})
+    return out
+
+
+def bench_fleet(n_inst: int, restarts: int = 8, iters: int = 2000, plain: bool = True):
+    """The constrained model at the paper's scale (12-33 missions, 4 planes and 8
+    helicopters, time limits, flight limit, helicopter-only missions): n_inst
+    instances x restarts, Tabu in the best form (iters iterations) and the sweep
+    form of Algorithms 2 (NS) and 3 (Tabu), each batch in one call on the wave
+    schedule."""
+    import torch
+
+    import paper_2002_11710_amd as at
+    from gen.instances import fleet_instance, fleet_specs, restart_seed
+
+    specs = fleet_specs(n_inst)
+    insts = [fleet_instance(s["seed"], s["n_missions"]) for s in specs]
+    devs = [at.DeviceInstance(at.build_travel(i.lat, i.lon, i.speed_heli), i.pickup, i.delivery,
+                              i.vehicle_loc, travel_plane=at.build_travel(i.lat, i.lon, i.speed_plane),
+                              vehicle_type=i.vehicle_type, deadline=i.deadline, heli_only=i.heli_only,
+                              flight_limit=i.flight_limit, horizon=i.horizon) for i in insts]
+    out = {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts}
+
+    def run(form, variant, n_it):
+        params = [at._capi.make_params(variant, s["tenure"], n_it, True, s["seed"], False,
+                                       form=form) for s in specs]
+        at.solve_batch(devs, params, restarts, allow_infeasible=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = at.solve_batch(devs, params, restarts, allow_infeasible=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ok = [r for r in res if r["status"] == 0]
+        assert all(r["status"] in (0, at.AT_EINFEAS) for r in res)
+        return res, {"wall_s": wall, "solves_per_s": len(res) / wall, "search_ms": float(res[0]["search_ms"]),
+                     "infeasible_starts": len(res) - len(ok),
+                     "mean_best_obj": float(sum(r["best_obj"] for r in ok) / max(1, len(ok))),
+                     "iters_done_total": int(sum(r["iters_done"] for r in ok))}
+
+    res, out["tabu_best"] = run(at.FORM_BEST, at.AT_TABU, iters)
+    out["tabu_best"]["iters"] = iters
+    slots = sum(restarts * iters * (s["n_missions"] * (s["n_missions"] + 12) + s["n_missions"] * (s["n_missions"] - 1) // 2)
+                for s in specs)
+    out["tabu_best"]["slot_evals_per_s"] = slots / out["tabu_best"]["wall_s"]
+    _, out["ns_sweep"] = run(at.FORM_SWEEP, at.AT_NS, 100000)
+    _, out["tabu_sweep"] = run(at.FORM_SWEEP, at.AT_TABU, 100000)
+    if plain:
+        # the plain per-instance form of the best-form batch: one at_solve per solve, in
+        # sequence, on the first solves of the batch (identical results)
+        n_p = min(len(res), 256)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_p):
+            i, r = k // restarts, k % restarts
+            try:
+                p = at.solve(devs[i], variant=at.AT_TABU, tenure=specs[i]["tenure"], iters=iters,
+                             restart_seed=restart_seed(specs[i]["seed"], r), trace=False)
+                assert p["best_obj"] == res[k]["best_obj"] and torch.equal(p["route_seq"], res[k]["route_seq"])
+            except at.AtError as e:
+                assert e.code == at.AT_EINFEAS and res[k]["status"] == at.AT_EINFEAS
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        out["tabu_best"].update(plain_sample_solves=n_p, plain_sample_s=t_plain,
+                                plain_solves_per_s=n_p / t_plain,
+                                speedup_vs_plain=out["tabu_best"]["solves_per_s"] / (n_p / t_plain))
     return out
 
 

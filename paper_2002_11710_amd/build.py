@@ -50,8 +50,16 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
     os.replace(tmp, LIB)
+    # the LDS bandwidth probe behind the roofline peak (a library of its own)
+    probe = os.path.join(HERE, "libldspeak.so")
+    cmd = [HIPCC, *CFLAGS, "-shared", "-o", probe + ".tmp", os.path.join(HERE, "ldspeak.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on ldspeak.hip")
+    os.replace(probe + ".tmp", probe)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", probe)
     return LIB
 
 

@@ -1,0 +1,84 @@
+// ldspeak.hip -- LDS read bandwidth and bank count of the GPU the library runs
+// on, for the roofline the move-delta kernels are measured against.
+//
+// Every thread of a full grid reads 32-bit words of a 64 KiB LDS buffer in a
+// loop: lane i of a wavefront reads word (base + i * stride) & mask, and a
+// thread's 16 reads of an iteration lie 1024 words apart (beyond the reach of
+// one paired-read instruction, so each is its own ds_read_b32).  With stride 1 the
+// 64 lanes touch 64 consecutive words: no bank conflicts, so the bytes read
+// over the kernel's time are the LDS read peak.  Larger strides make lanes
+// share banks; the time against the stride gives the number of banks (the
+// smallest stride at which all lanes that a cycle serves fall into one bank).
+// One thread also reads the shader clock and the 100 MHz wall clock around
+// its loop, which gives the clock the kernel ran at.  Every iteration moves
+// each thread's reads by 17 words, so no read repeats an earlier one and none
+// can be lifted out of the loop; the lane pattern, and with it the banks the
+// lanes hit, stays the same.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kWords = 16384;           // 64 KiB
+constexpr int kUnroll = 16;
+
+__global__ void __launch_bounds__(1024) k_lds_read(int iters, int stride, uint32_t *sink, uint64_t *clocks)
+{
+    __shared__ uint32_t buf[kWords];
+    for (int k = threadIdx.x; k < kWords; k += blockDim.x) buf[k] = (uint32_t)k * 2654435761u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int base = (wave * 64 * stride + lane * stride) & (kWords - 1);
+    uint32_t acc = 0;
+    const uint64_t c0 = clock64(), w0 = wall_clock64();
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) acc += buf[(base + i * 17 + u * 1024) & (kWords - 1)];
+    }
+    const uint64_t c1 = clock64(), w1 = wall_clock64();
+    if (acc == 0x12345678u) sink[blockIdx.x] = acc;   // keeps the reads alive
+    if (blockIdx.x == 0 && threadIdx.x == 0) { clocks[0] = c1 - c0; clocks[1] = w1 - w0; }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Run the read loop on `blocks` workgroups of 1024 threads, `iters` x 16
+// reads per thread, lane stride `stride` words.  Writes the kernel time (ms,
+// HIP events), and the shader clocks and 100 MHz ticks one thread counted.
+// Returns 0, or the HIP error.
+int ldspeak_run(int blocks, int iters, int stride, double *ms, uint64_t *shader_clocks,
+                uint64_t *wall_ticks)
+{
+    uint32_t *sink = nullptr;
+    uint64_t *clk = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipMalloc((void **)&sink, sizeof(uint32_t) * (size_t)blocks);
+    if (e == hipSuccess) e = hipMalloc((void **)&clk, 2 * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_lds_read, dim3(blocks), dim3(1024), 0, 0, 1, stride, sink, clk);   // warm-up
+        (void)hipEventRecord(a, 0);
+        hipLaunchKernelGGL(k_lds_read, dim3(blocks), dim3(1024), 0, 0, iters, stride, sink, clk);
+        (void)hipEventRecord(b, 0);
+        e = hipEventSynchronize(b);
+    }
+    if (e == hipSuccess) {
+        float f = 0.f;
+        e = hipEventElapsedTime(&f, a, b);
+        *ms = f;
+    }
+    uint64_t h[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpy(h, clk, sizeof(h), hipMemcpyDeviceToHost);
+    *shader_clocks = h[0];
+    *wall_ticks = h[1];
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (sink) (void)hipFree(sink);
+    if (clk) (void)hipFree(clk);
+    return (int)e;
+}
+
+}  // extern "C"
