@@ -137,9 +137,9 @@ def lds_peak(strides=(1, 2, 4, 8, 16, 32, 64, 128)):
             raise RuntimeError(f"ldspeak_run: HIP error {rc}")
         return ms.value, clk.value, wt.value
 
-    iters = 20000
+    iters = 40000
     ms, clk, wt = run(iters, 1)
-    nbytes = blocks * 1024 * iters * 16 * 4
+    nbytes = blocks * 1024 * iters * 8 * 4       # 8 reads of 4 bytes per thread and iteration
     ghz = clk / (wt / 100e6) / 1e9 if wt else None
     out = {"bytes": nbytes, "ms": ms, "TBps": nbytes / (ms / 1000.0) / 1e12, "cus": cus,
            "shader_GHz": ghz,

@@ -312,6 +312,20 @@ static int plan_wave(JobHost &h, const InstDev &d)
     const bool two = d.T2 != nullptr;
     const int esz = constrained(d) ? 4 : d.esz;
     h.kind = AT_SCHED_WAVE;
+    h.wtile = !constrained(d) && h.pr.form == AT_FORM_BEST;
+    if (h.wtile) {
+        // the unconstrained best form: the one-workgroup schedule's code on one wavefront
+        h.tb16 = tabu_bytes(h.pr) == 2 ? 1 : 0;
+        h.esz16 = d.esz == 2 ? 1 : 0;
+        h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
+        h.chunk = pick_chunk(h.pr, h.slots);
+        h.rchunk = std::min(64, 2 * h.chunk);
+        h.groups = 1;
+        h.block = kWave;
+        if (h.lds > kLdsLimit)
+            return fail(AT_ENOMEM, "instance too large for the wave schedule (%u bytes of LDS per solve)", h.lds);
+        return AT_OK;
+    }
     h.esz16 = esz == 2 ? 1 : 0;
     h.tb16 = 0;
     h.lds = wave_lds_bytes(d.M, d.V, d.R, d.Cs, esz, two);
@@ -362,7 +376,7 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     }
     h.kind = AT_SCHED_WG;
     if (!h.chunked && h.pr.schedule == AT_SCHED_AUTO && pick_wave(h.slots) &&
-        wave_lds_bytes(d.M, d.V, d.R, d.Cs, d.esz, false) <= kLdsLimit / 2)
+        lds_layout(d.M, d.V, d.R, d.Cs, d.esz, tabu_bytes(h.pr)).total <= kLdsLimit / 2)
         return plan_wave(h, d);
     if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
         // measured on gfx950 (16 x 400 missions): 512 threads, 8-column swap units
@@ -482,16 +496,18 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
 {
     hipError_t e;
     const int n = (int)order.size();
-    struct Cls { int k0, k1, kind, block, tb16, esz16; uint32_t lds; };
+    struct Cls { int k0, k1, kind, block, tb16, esz16; bool wtile; uint32_t lds; };
     std::vector<Cls> cls;
     int k = 0;
     auto one_per_solve = [](int kind) { return kind == AT_SCHED_WG || kind == AT_SCHED_WAVE; };
     while (k < n && one_per_solve(jobs[(size_t)order[(size_t)k]].kind)) {
         const JobHost &hf = jobs[(size_t)order[(size_t)k]];
-        Cls c{k, k, hf.kind, hf.block, hf.tb16, hf.esz16, 0};
+        Cls c{k, k, hf.kind, hf.block, hf.tb16, hf.esz16, hf.wtile, 0};
         while (c.k1 < n) {
             const JobHost &h = jobs[(size_t)order[(size_t)c.k1]];
-            if (h.kind != hf.kind || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block) break;
+            if (h.kind != hf.kind || h.esz16 != hf.esz16 || h.tb16 != hf.tb16 || h.block != hf.block ||
+                h.wtile != hf.wtile)
+                break;
             c.lds = std::max(c.lds, h.lds);
             ++c.k1;
         }
@@ -526,7 +542,9 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
                 const int by_lds = std::max(1, (int)((kLdsLimit + 64) / (per * (uint32_t)wpg)));
                 const int per_cu = std::min(by_lds, 16 / wpg);
                 const int grid = std::max(1, std::min((count + wpg - 1) / wpg, num_cus() * per_cu));
-                e = launch_search_wave(dj + q.k0, count, &xs->queues[c], grid, wpg, per, q.esz16, st);
+                e = q.wtile ? launch_search_wg_wave(dj + q.k0, count, &xs->queues[c], grid, wpg, per, q.tb16,
+                                                    q.esz16, st)
+                            : launch_search_wave(dj + q.k0, count, &xs->queues[c], grid, wpg, per, q.esz16, st);
             } else {
                 const int by_lds = std::max(1, (int)((kLdsLimit + 64) / std::max<uint32_t>(q.lds, 1)));
                 const int by_waves = std::max(1, 16 * kWave / q.block);
@@ -593,7 +611,8 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
         const int cx = grp(x.kind), cy = grp(y.kind);
         if (cx != cy) return cx < cy;
         if (x.kind == AT_SCHED_WG || x.kind == AT_SCHED_GLOBAL || x.kind == AT_SCHED_WAVE) {
-            const int kx = (x.esz16 * 2 + x.tb16) * 4096 + x.block, ky = (y.esz16 * 2 + y.tb16) * 4096 + y.block;
+            const int kx = ((x.wtile * 2 + x.esz16) * 2 + x.tb16) * 4096 + x.block;
+            const int ky = ((y.wtile * 2 + y.esz16) * 2 + y.tb16) * 4096 + y.block;
             if (kx != ky) return kx > ky;
         }
         return x.slots > y.slots;

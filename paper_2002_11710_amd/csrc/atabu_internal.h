@@ -236,6 +236,9 @@ int64_t prepare_chunks(const InstDev &h, int64_t *fill_chunks);
 hipError_t launch_prepare(InstDev *insts, int32_t n, int64_t scan_chunks, int64_t fill_chunks, hipStream_t s);
 hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid, int block,
                             uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
+hipError_t launch_search_wg_wave(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid,
+                                 int waves_per_group, uint32_t lds_per_solve, int tb16, int esz16,
+                                 hipStream_t s);
 hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,

@@ -34,6 +34,7 @@ struct JobHost {
     int g0 = 0, launch = 0;           // global schedule: first workgroup, launch index (assign_groups)
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
     bool chunked = false;             // run in chunks of iterations (serving): no wave schedule
+    bool wtile = false;               // wave schedule on the one-workgroup code (unconstrained best form)
 };
 
 int fail(int code, const char *fmt, ...);

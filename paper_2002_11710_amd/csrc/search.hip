@@ -54,6 +54,21 @@ struct Ctx {
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// Barrier of the threads that run one solve: the workgroup, or (WAVE) one
+// wavefront, whose lanes run in lockstep: then only the LDS writes before it
+// must be seen by the reads after it.
+template <bool WAVE>
+__device__ __forceinline__ void bsync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Global-memory views of a pointer: accesses through them compile to global_*
 // instructions, which count on the vector-memory counter only.  The flat
 // instructions a generic pointer gets also hold the LDS counter, so every LDS
@@ -605,7 +620,7 @@ __device__ __forceinline__ void index_routes(const Ctx &c, int tid, int nthr)
 // Algorithm 1 without feasibility checks: missions in a SplitMix64-driven
 // Fisher-Yates order (identity for seed 0), each appended to the vehicle whose
 // route time grows least (ties to the lowest vehicle).  Returns the objective.
-template <typename TE>
+template <typename TE, bool WAVE = false>
 __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc_sum, int tid,
                           int nthr)
 {
@@ -619,14 +634,14 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
         if (i >= 1) draw[i] = (int32_t)(splitmix_at(seed, (uint64_t)(M - i)) % (uint64_t)(i + 1));
     }
     for (int v = tid; v < V; v += nthr) { lastx[v] = c.vrow[v]; cnt[v] = 0; }
-    __syncthreads();
+    bsync<WAVE>();
     if (seed != 0 && tid == 0) {
         for (int i = M - 1; i >= 1; --i) {
             const int j = draw[i];
             const int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
         }
     }
-    __syncthreads();
+    bsync<WAVE>();
     if (tid < kWave) {
         const int lane = tid;
         int64_t acc = 0;
@@ -647,7 +662,7 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
         }
         if (lane == 0) c.red[100] = (uint64_t)acc;
     }
-    __syncthreads();
+    bsync<WAVE>();
     if (tid == 0) {
         int o = 0;
         for (int v = 0; v < V; ++v) { c.off[v] = o; curv[v] = o; o += cnt[v]; }
@@ -657,10 +672,10 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
             c.seq[curv[v]++] = (uint16_t)pi[s];
         }
     }
-    __syncthreads();
+    bsync<WAVE>();
     index_routes(c, tid, nthr);
     const int64_t acc = (int64_t)c.red[100];
-    __syncthreads();
+    bsync<WAVE>();
     return acc + svc_sum;
 }
 
@@ -746,11 +761,13 @@ __device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int la
     }
 }
 
-template <typename TE, typename TB, bool MULTI>
+template <typename TE, typename TB, bool MULTI, bool WAVE = false>
 __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 {
     const InstDev &I = *J.inst;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    // WAVE: one wavefront runs the solve in its own LDS region
+    const int tid = WAVE ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
+    const int nthr = WAVE ? kWave : (int)blockDim.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
     const int M = I.M, V = I.V;
     const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), (int)sizeof(TB));
@@ -760,7 +777,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     const bool writer = !MULTI || wg == 0;
 
     load_instance<TE>(I, c, tc, tid, nthr);
-    __syncthreads();
+    bsync<WAVE>();
 
     int64_t cur, best;
     int best_iter, stopped;
@@ -773,17 +790,17 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         best = st->best;
         best_iter = st->best_iter;
         stopped = st->stopped;
-        __syncthreads();
+        bsync<WAVE>();
         index_routes(c, tid, nthr);
-        __syncthreads();
+        bsync<WAVE>();
     } else {
-        cur = greedy<TE>(c, tc, J.seed, I.svc_sum, tid, nthr);
+        cur = greedy<TE, WAVE>(c, tc, J.seed, I.svc_sum, tid, nthr);
         for (int k = tid; k < M * V; k += nthr) tabu[k] = (TB)0;
         best = cur;
         best_iter = -1;
         stopped = 0;
         if (writer) snapshot(c, J, tid, nthr);
-        __syncthreads();
+        bsync<WAVE>();
     }
 
     const bool use_tabu = J.variant == AT_TABU;
@@ -793,7 +810,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
     bool aborted = false;
     for (; t < J.t_end && !stopped; ++t) {
         prep<TE>(c, tc, tid, nthr);
-        __syncthreads();
+        bsync<WAVE>();
         int thr = INT32_MIN;
         if (J.aspiration) {
             const int64_t g = best - cur;
@@ -802,7 +819,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
         uint64_t k = eval_all<TE, TB, MULTI>(c, tc, tabu, gw, TW, us0, lane, t, thr, use_tabu);
         k = wave_min(k);
         if (lane == 0) c.red[wave] = k;
-        __syncthreads();
+        bsync<WAVE>();
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
             w = wave_min(w);
@@ -893,7 +910,7 @@ __device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
                 if (use_tabu || dw < 0) apply_wave(c, mv, lane);
             }
         }
-        __syncthreads();   // the move is decoded and applied
+        bsync<WAVE>();   // the move is decoded and applied
         if (MULTI && c.red[65]) { aborted = true; break; }
         const uint64_t key = c.red[64];
         if (key == kKeyNone) {
@@ -1681,6 +1698,26 @@ __global__ void __launch_bounds__(1024) k_search_wg(const JobDev *jobs, int n_jo
     }
 }
 
+// One wavefront per job: each wavefront takes jobs from the atomic queue and
+// runs them in its own LDS region (lds_per_solve bytes at its index in the
+// workgroup) with the one-workgroup schedule's code, its barriers wavefront-
+// wide.
+template <typename TE, typename TB>
+__global__ void __launch_bounds__(256) k_search_wg_wave(const JobDev *jobs, int n_jobs, uint32_t *queue,
+                                                       uint32_t lds_per_solve)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    char *base = smem + (size_t)wave * lds_per_solve;
+    for (;;) {
+        int j = 0;
+        if (lane == 0) j = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        j = __shfl(j, 0, kWave);
+        if (j >= n_jobs) return;
+        run_job<TE, TB, false, true>(jobs[j], base, 0, 1, nullptr);
+    }
+}
+
 template <typename TE, typename TB>
 __global__ void __launch_bounds__(1024) k_search_multi(const JobDev *job, Xchg *xs)
 {
@@ -1762,6 +1799,26 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue,
     else if (tb16) AT_WG(int32_t, uint16_t);
     else AT_WG(int32_t, int32_t);
 #undef AT_WG
+    return hipGetLastError();
+}
+
+hipError_t launch_search_wg_wave(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid,
+                                 int waves_per_group, uint32_t lds_per_solve, int tb16, int esz16,
+                                 hipStream_t s)
+{
+    hipError_t e;
+    const uint32_t lds = lds_per_solve * (uint32_t)waves_per_group;
+#define AT_WW(TE, TB)                                                                          \
+    do {                                                                                       \
+        if ((e = set_lds(k_search_wg_wave<TE, TB>, lds)) != hipSuccess) return e;              \
+        hipLaunchKernelGGL((k_search_wg_wave<TE, TB>), dim3(grid), dim3(kWave * waves_per_group), lds, \
+                           s, jobs, n_jobs, queue, lds_per_solve);                             \
+    } while (0)
+    if (esz16 && tb16) AT_WW(uint16_t, uint16_t);
+    else if (esz16) AT_WW(uint16_t, int32_t);
+    else if (tb16) AT_WW(int32_t, uint16_t);
+    else AT_WW(int32_t, int32_t);
+#undef AT_WW
     return hipGetLastError();
 }
 

@@ -2,25 +2,27 @@
 // on, for the roofline the move-delta kernels are measured against.
 //
 // Every thread of a full grid reads 32-bit words of a 64 KiB LDS buffer in a
-// loop: lane i of a wavefront reads word (base + i * stride) & mask, and a
-// thread's 16 reads of an iteration lie 1024 words apart (beyond the reach of
-// one paired-read instruction, so each is its own ds_read_b32).  With stride 1 the
-// 64 lanes touch 64 consecutive words: no bank conflicts, so the bytes read
-// over the kernel's time are the LDS read peak.  Larger strides make lanes
-// share banks; the time against the stride gives the number of banks (the
-// smallest stride at which all lanes that a cycle serves fall into one bank).
-// One thread also reads the shader clock and the 100 MHz wall clock around
-// its loop, which gives the clock the kernel ran at.  Every iteration moves
-// each thread's reads by 17 words, so no read repeats an earlier one and none
-// can be lifted out of the loop; the lane pattern, and with it the banks the
-// lanes hit, stays the same.
+// loop: lane i of a wavefront starts at word (i * stride) mod 1024, and a
+// thread's 8 reads of an iteration lie 2047 words apart (more than a paired
+// read reaches and no multiple of 64 words, so each is its own ds_read_b32,
+// and its offset is an immediate of the instruction: one address add per iteration, one
+// accumulate per read, so the vector ALU never limits the LDS).  With stride 1
+// the 64 lanes touch 64 consecutive words: no bank conflicts, so the bytes
+// read over the kernel's time are the LDS read peak.  Larger strides make
+// lanes share banks; the time against the stride gives the number of banks
+// (the smallest stride beyond which the time stops growing).  One thread also
+// reads the shader clock and the 100 MHz wall clock around its loop, which
+// gives the clock the kernel ran at.  Every iteration moves each thread's reads
+// by 17 words (mod 1024), so no read can be lifted out of the loop; the lane
+// pattern, and with it the banks the lanes hit, stays the same.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace {
 
 constexpr int kWords = 16384;           // 64 KiB
-constexpr int kUnroll = 16;
+constexpr int kUnroll = 8;              // reads per iteration, kSpread words apart
+constexpr int kSpread = 2047;
 
 __global__ void __launch_bounds__(1024) k_lds_read(int iters, int stride, uint32_t *sink, uint64_t *clocks)
 {
@@ -28,12 +30,14 @@ __global__ void __launch_bounds__(1024) k_lds_read(int iters, int stride, uint32
     for (int k = threadIdx.x; k < kWords; k += blockDim.x) buf[k] = (uint32_t)k * 2654435761u;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int base = (wave * 64 * stride + lane * stride) & (kWords - 1);
+    const int base = (wave * 64 * stride + lane * stride) & 1023;
     uint32_t acc = 0;
     const uint64_t c0 = clock64(), w0 = wall_clock64();
     for (int i = 0; i < iters; ++i) {
+        // p + 7 * kSpread <= 2046 + 14329 < kWords: every read stays inside the buffer
+        const uint32_t *q = buf + base + ((i * 17) & 1023);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) acc += buf[(base + i * 17 + u * 1024) & (kWords - 1)];
+        for (int u = 0; u < kUnroll; ++u) acc += q[u * kSpread];
     }
     const uint64_t c1 = clock64(), w1 = wall_clock64();
     if (acc == 0x12345678u) sink[blockIdx.x] = acc;   // keeps the reads alive

@@ -65,6 +65,21 @@ def test_wave_unconstrained_trajectories(maker):
         assert_same_result(o, g, f"wave M={inst.n_missions} variant {variant} tenure {tenure} seed {seed}")
 
 
+@pytest.mark.parametrize("maker", [lambda: small_instance(0), lambda: make_instance(8, 100, 5, 12, 64)])
+def test_wave_generic_kernel_unconstrained(maker):
+    """The wave kernel of the constrained model with every constraint switched
+    off in substance (the plane matrix is the helicopter one, every vehicle a
+    helicopter) runs the unconstrained search: equal to the oracle."""
+    inst = maker()
+    T = at.build_travel(inst.lat, inst.lon)
+    dev = at.DeviceInstance(T, inst.pickup, inst.delivery, inst.vehicle_loc, travel_plane=T,
+                            vehicle_type=np.zeros(inst.n_vehicles, np.int32))
+    for variant, tenure, seed in ((at.AT_TABU, 7, 0), (at.AT_NS, 7, 0), (at.AT_TABU, 3, 17)):
+        _, o = oracle_solve(inst, variant=variant, tenure=tenure, iters=200, restart_seed=seed)
+        g = at.solve(dev, variant=variant, tenure=tenure, iters=200, restart_seed=seed)
+        assert_same_result(o, g, f"generic wave M={inst.n_missions} variant {variant} seed {seed}")
+
+
 def test_wave_unconstrained_keys():
     inst = make_instance(8, 100, 5, 12, 64)
     P = oracle.Problem.from_instance(inst)
