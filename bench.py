@@ -94,10 +94,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=4096,
                     help="also time an uneven batch of this many instances x 8 restarts (0: skip)")
-    ap.add_argument("--serve", type=str, default="100,1000,5000",
-                    help="also run the serving stream at these arrival rates (req/s, comma separated; "
-                         "empty: skip)")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve", type=str, default="200,400,inf",
+                    help="also run the serving stream at these arrival rates (req/s, comma separated, "
+                         "'inf': every request at time 0, the saturation throughput; empty: skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-plain", type=int, default=400,
+                    help="requests of the stream also solved one at_solve at a time (the plain form)")
     ap.add_argument("--serve-chunk", type=int, default=50, help="iterations per serving launch")
     ap.add_argument("--serve-slots", type=int, default=256, help="concurrent solves in the server")
     ap.add_argument("--stress", type=int, default=1000,
@@ -383,21 +385,24 @@ def main():
                        pmc_valu_busy_frac=k.get("valu_busy"))
         line["lds_roofline"] = lds
     if not args.no_lds_peak:
+        # the LDS roofline's peak is the measured one (conflict-free ds_read_b32 over the
+        # whole GPU, at the clock it ran at); the nominal 128 B/clk/CU at 2.4 GHz beside it
         line["lds_peak"] = lds_peak()
         if "lds_roofline" in line:
             pk = line["lds_peak"]["TBps"] * 1e12
-            line["lds_roofline"].update(measured_peak_GBps=pk / 1e9,
-                                        frac_of_measured=line["batch"]["lds_bytes_per_s"] / pk)
+            line["lds_roofline"].update(peak_GBps=pk / 1e9, frac=line["batch"]["lds_bytes_per_s"] / pk,
+                                        peak_source="measured (ldspeak)",
+                                        nominal_peak_GBps=LDS_PEAK_BPS / 1e9,
+                                        frac_of_nominal=line["batch"]["lds_bytes_per_s"] / LDS_PEAK_BPS)
     if args.fleet:
         line["fleet"] = bench_fleet(args.fleet, plain=not args.no_plain)
     if args.stress:
         line["stress"] = bench_stress(args.stress)
     if args.serve:
         rates = [float(x) for x in args.serve.split(",")]
-        line["serving"] = [bench_serve(lam, args.serve_requests, chunk=args.serve_chunk,
-                                       slots=args.serve_slots,
-                                       plain_sample=32 if k == len(rates) - 1 and not args.no_plain else 0)
-                           for k, lam in enumerate(rates)]
+        line["serving"] = bench_serve_sweep(rates, args.serve_requests, chunk=args.serve_chunk,
+                                            slots=args.serve_slots,
+                                            plain=0 if args.no_plain else args.serve_plain)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(line), flush=True)
@@ -424,15 +429,11 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     devs = [at.DeviceInstance.from_instance(i) for i in insts]
     params = [at._capi.make_params(at.AT_TABU, s["tenure"], s["iters"], True, s["seed"], False)
               for s in specs]
-    outs = []
-    for i in insts:
-        for _ in range(restarts):
-            outs.append(at._capi._alloc_result(i.n_missions, i.n_vehicles, 2000, False, "cuda"))
-    ws = None
-    res = at.solve_batch(devs, params, restarts, outs=outs)   # warm-up
+    res = at.solve_batch_flat(devs, params, restarts)   # warm-up; its buffers are reused
+    ws = torch.empty(at.workspace_size(devs, params, restarts), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = at.solve_batch(devs, params, restarts, outs=outs)
+    res = at.solve_batch_flat(devs, params, restarts, ws=ws, bufs=res)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     evals = 0
@@ -443,8 +444,8 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
         evals += restarts * 2000 * (rel + swp)
         ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
         lds += restarts * 2000 * (rel * LDS_RELOCATE + swp * LDS_SWAP)
-    kms = float(res[0]["search_ms"])
-    assert all(r["status"] == 0 for r in res)
+    kms = float(res.search_ms[0])
+    assert (res.status == 0).all()
     out = {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
            "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
            "move_evals_per_s": evals / wall, "search_ms": kms,
@@ -455,7 +456,7 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     # the plain per-instance form: one at_solve launch per (instance, restart), in
     # sequence on one stream, on a sample of the same solves (identical results)
     from gen.instances import restart_seed
-    n_plain = min(len(res), 64)
+    n_plain = min(res.n, 64)
     pairs = [(k // restarts, k % restarts) for k in range(n_plain)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -464,14 +465,14 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     for (i, r), p in zip(pairs, plain):
-        b = res[i * restarts + r]
-        assert p["best_obj"] == b["best_obj"] and torch.equal(p["route_seq"], b["route_seq"])
+        k = i * restarts + r
+        assert p["best_obj"] == res.best_obj[k] and torch.equal(p["route_seq"], res.route_seq(k))
     plain_work = sum(move_counts(specs[i]["n_missions"], specs[i]["n_vehicles"])[0]
                      + move_counts(specs[i]["n_missions"], specs[i]["n_vehicles"])[1] for i, _ in pairs)
     all_work = sum(restarts * sum(move_counts(s["n_missions"], s["n_vehicles"])) for s in specs)
     # plain solves/s for this batch's mix: the sample's move-eval rate applied to all solves
     plain_evals_per_s = plain_work * 2000 / t_plain
-    plain_sps = plain_evals_per_s / (all_work * 2000 / len(res))
+    plain_sps = plain_evals_per_s / (all_work * 2000 / res.n)
     out.update({"plain_sample_solves": n_plain, "plain_sample_s": t_plain,
                 "plain_solves_per_s": plain_sps,
                 "speedup_vs_plain": (n_inst * restarts / wall) / plain_sps})
@@ -500,18 +501,19 @@ def bench_fleet(n_inst: int, restarts: int = 8, iters: int = 2000, plain: bool =
     def run(form, variant, n_it):
         params = [at._capi.make_params(variant, s["tenure"], n_it, True, s["seed"], False,
                                        form=form) for s in specs]
-        at.solve_batch(devs, params, restarts, allow_infeasible=True)
+        res = at.solve_batch_flat(devs, params, restarts, allow_infeasible=True)
+        ws = torch.empty(at.workspace_size(devs, params, restarts), dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = at.solve_batch(devs, params, restarts, allow_infeasible=True)
+        res = at.solve_batch_flat(devs, params, restarts, ws=ws, allow_infeasible=True, bufs=res)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ok = [r for r in res if r["status"] == 0]
-        assert all(r["status"] in (0, at.AT_EINFEAS) for r in res)
-        return res, {"wall_s": wall, "solves_per_s": len(res) / wall, "search_ms": float(res[0]["search_ms"]),
-                     "infeasible_starts": len(res) - len(ok),
-                     "mean_best_obj": float(sum(r["best_obj"] for r in ok) / max(1, len(ok))),
-                     "iters_done_total": int(sum(r["iters_done"] for r in ok))}
+        ok = res.status == 0
+        assert ((res.status == 0) | (res.status == at.AT_EINFEAS)).all()
+        return res, {"wall_s": wall, "solves_per_s": res.n / wall, "search_ms": float(res.search_ms[0]),
+                     "infeasible_starts": int((~ok).sum()),
+                     "mean_best_obj": float(res.best_obj[ok].mean()),
+                     "iters_done_total": int(res.iters_done[ok].sum())}
 
     res, out["tabu_best"] = run(at.FORM_BEST, at.AT_TABU, iters)
     out["tabu_best"]["iters"] = iters
@@ -523,7 +525,7 @@ def bench_fleet(n_inst: int, restarts: int = 8, iters: int = 2000, plain: bool =
     if plain:
         # the plain per-instance form of the best-form batch: one at_solve per solve, in
         # sequence, on the first solves of the batch (identical results)
-        n_p = min(len(res), 256)
+        n_p = min(res.n, 128)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(n_p):
@@ -531,9 +533,9 @@ def bench_fleet(n_inst: int, restarts: int = 8, iters: int = 2000, plain: bool =
             try:
                 p = at.solve(devs[i], variant=at.AT_TABU, tenure=specs[i]["tenure"], iters=iters,
                              restart_seed=restart_seed(specs[i]["seed"], r), trace=False)
-                assert p["best_obj"] == res[k]["best_obj"] and torch.equal(p["route_seq"], res[k]["route_seq"])
+                assert p["best_obj"] == res.best_obj[k] and torch.equal(p["route_seq"], res.route_seq(k))
             except at.AtError as e:
-                assert e.code == at.AT_EINFEAS and res[k]["status"] == at.AT_EINFEAS
+                assert e.code == at.AT_EINFEAS and res.status[k] == at.AT_EINFEAS
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         out["tabu_best"].update(plain_sample_solves=n_p, plain_sample_s=t_plain,
@@ -567,11 +569,14 @@ def bench_stress(iters: int):
     return out
 
 
-def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,
-                budget: int = 64 << 30, plain_sample: int = 0):
-    """Open-loop Poisson stream of n_req requests at rate lam through the
-    continuous-batching server; latency = result on the host minus scheduled
-    arrival.  Instances are uploaded before the clock starts."""
+def bench_serve_sweep(rates, n_req: int, chunk: int = 50, slots: int = 256, budget: int = 64 << 30,
+                      plain: int = 0):
+    """Open-loop Poisson streams of n_req requests through the continuous-batching
+    server, one per arrival rate (inf: every request arrives at time 0, which
+    measures the saturation throughput); latency = result on the host minus the
+    scheduled arrival.  Instances are uploaded before any clock starts.  Then the
+    plain per-request form on the stream's first `plain` requests, one at_solve
+    each in arrival order, each result checked equal to the served one."""
     import numpy as np
     import torch
 
@@ -579,56 +584,69 @@ def bench_serve(lam: float, n_req: int, chunk: int = 50, slots: int = 256,
     from gen.instances import make_instance, poisson_arrivals, serve_specs
 
     specs = serve_specs(n_req)
-    arrivals = poisson_arrivals(n_req, lam, stream_seed=2 + int(lam))
     devs = [at.DeviceInstance.from_instance(make_instance(s["seed"], s["n_fac"], s["n_bases"],
                                                           s["n_vehicles"], s["n_missions"]))
             for s in specs]
     torch.cuda.synchronize()
-    srv = at.Server(budget, max_slots=slots, chunk_iters=chunk)
-    done = {}
-    submitted = 0
-    tickets = {}
-    t0 = time.perf_counter()
-    while len(done) < n_req:
-        now = time.perf_counter() - t0
-        while submitted < n_req and arrivals[submitted] <= now:
-            s = specs[submitted]
-            tickets[srv.submit(devs[submitted], tenure=s["tenure"], iters=s["iters"],
-                               trace=False)] = submitted
-            submitted += 1
-        srv.progress()
-        for tk in list(tickets):
-            r = srv.poll(tk)
-            if r is not None:
-                k = tickets.pop(tk)
-                assert r["status"] == 0
-                done[k] = time.perf_counter() - t0
-        if not tickets and submitted < n_req:
-            time.sleep(max(0.0, min(0.001, arrivals[submitted] - (time.perf_counter() - t0))))
-    wall = time.perf_counter() - t0
-    srv.close()
-    lat = np.array([done[k] - arrivals[k] for k in range(n_req)]) * 1000.0
-    out = {"lambda_req_per_s": lam, "requests": n_req, "wall_s": wall,
-           "solves_per_s": n_req / wall, "p50_ms": float(np.percentile(lat, 50)),
-           "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
-           "chunk_iters": chunk, "max_slots": slots}
-    if plain_sample:
-        # the plain per-instance form: one at_solve per request, in arrival order, on
-        # a sample of the stream; its move-eval rate applied to the stream's mix
-        work = [sum(move_counts(s["n_missions"], s["n_vehicles"])) * s["iters"] for s in specs]
-        n_p = min(plain_sample, n_req)
+    work = [sum(move_counts(s["n_missions"], s["n_vehicles"])) * s["iters"] for s in specs]
+    out = {"requests_per_rate": n_req, "chunk_iters": chunk, "max_slots": slots,
+           "hbm_budget_GiB": budget >> 30, "move_evals_per_stream": float(sum(work)), "rates": []}
+    served = None
+    for lam in rates:
+        arrivals = (np.zeros(n_req) if lam == float("inf")
+                    else poisson_arrivals(n_req, lam, stream_seed=2 + int(lam)))
+        srv = at.Server(budget, max_slots=slots, chunk_iters=chunk)
+        done, res = {}, {}
+        submitted = 0
+        tickets = {}
+        t0 = time.perf_counter()
+        while len(done) < n_req:
+            now = time.perf_counter() - t0
+            while submitted < n_req and arrivals[submitted] <= now:
+                s = specs[submitted]
+                tickets[srv.submit(devs[submitted], tenure=s["tenure"], iters=s["iters"],
+                                   trace=False)] = submitted
+                submitted += 1
+            srv.progress()
+            for tk in list(tickets):
+                r = srv.poll(tk)
+                if r is not None:
+                    k = tickets.pop(tk)
+                    assert r["status"] == 0
+                    done[k] = time.perf_counter() - t0
+                    if k < plain:
+                        res[k] = (int(r["best_obj"]), r["route_seq"].cpu())
+            if not tickets and submitted < n_req:
+                time.sleep(max(0.0, min(0.001, arrivals[submitted] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([done[k] - arrivals[k] for k in range(n_req)]) * 1000.0
+        out["rates"].append({"lambda_req_per_s": lam if lam != float("inf") else "inf",
+                             "wall_s": wall, "solves_per_s": n_req / wall,
+                             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "max_ms": float(lat.max())})
+        served = served or res
+    sat = [r for r in out["rates"] if r["lambda_req_per_s"] == "inf"]
+    if sat:
+        out["saturation_solves_per_s"] = sat[0]["solves_per_s"]
+    if plain:
+        n_p = min(plain, n_req)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(n_p):
             s = specs[k]
             r = at.solve(devs[k], variant=at.AT_TABU, tenure=s["tenure"], iters=s["iters"], trace=False)
             assert r["status"] == 0
+            assert int(r["best_obj"]) == served[k][0] and torch.equal(r["route_seq"].cpu(), served[k][1]), k
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t1
-        plain_sps = (sum(work[:n_p]) / t_plain) / (sum(work) / n_req)
-        out.update({"plain_sample_solves": n_p, "plain_sample_s": t_plain,
-                    "plain_solves_per_s": plain_sps,
-                    "speedup_vs_plain": (n_req / wall) / plain_sps})
+        share = sum(work[:n_p]) / sum(work)
+        out.update({"plain_requests": n_p, "plain_s": t_plain, "plain_solves_per_s": n_p / t_plain,
+                    "plain_share_of_stream_work": share,
+                    "note": f"the plain form was timed on the stream's first {n_p} requests "
+                            f"({share:.1%} of its move evaluations), every result equal to the served one"})
+        if sat:
+            out["speedup_vs_plain"] = sat[0]["solves_per_s"] / (n_p / t_plain)
     return out
 
 

@@ -11,13 +11,13 @@ from ._capi import (  # noqa: F401
     FORM_BEST, FORM_SWEEP, SCHED_AUTO, SCHED_GLOBAL, SCHED_MULTI, SCHED_WAVE, SCHED_WG, AtError,
     DeviceInstance, Server,
     build_travel, build_travel_device, debug_eval_moves, lib, lib_path, solve, solve_batch,
-    shutdown, solve_noalloc, symbols, workspace_size,
+    BatchResult, shutdown, solve_batch_flat, solve_noalloc, symbols, workspace_size,
 )
 
 __all__ = [
     "AT_OK", "AT_EINVAL", "AT_ERANGE", "AT_ENOMEM", "AT_EAGAIN", "AT_EDEVICE", "AT_EINFEAS",
     "AT_TABU", "AT_NS", "FORM_BEST", "FORM_SWEEP", "SCHED_AUTO", "SCHED_WG", "SCHED_MULTI",
-    "SCHED_GLOBAL", "SCHED_WAVE", "AtError",
+    "SCHED_GLOBAL", "SCHED_WAVE", "AtError", "BatchResult", "solve_batch_flat",
     "DeviceInstance", "Server", "build_travel", "build_travel_device", "debug_eval_moves",
     "lib", "lib_path", "shutdown", "solve", "solve_batch", "solve_noalloc", "symbols",
     "workspace_size",

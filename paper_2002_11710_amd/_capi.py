@@ -325,6 +325,94 @@ def solve_batch(insts, params, n_restarts=1, ws=None, stream=None, outs=None,
     return [_finish(outs[k], ra[k], insts[k // n_restarts].n_missions) for k in range(len(outs))]
 
 
+class BatchResult:
+    """Results of solve_batch_flat, solve k = (instance k // n_restarts, restart
+    k % n_restarts): per-solve scalars as numpy arrays; the best routes of all
+    solves in two flat device tensors (route_off of solve k at
+    off_all[off_start[k]:off_start[k+1]], its route_seq at
+    seq_all[seq_start[k]:seq_start[k+1]]), and optionally the final routes
+    likewise."""
+
+    def __init__(self, n, off_start, seq_start, bufs):
+        self.n = n
+        self.off_start, self.seq_start = off_start, seq_start
+        self.off_all, self.seq_all, self.of_all = bufs["off"], bufs["seq"], bufs["of"]
+        self.fin_off_all, self.fin_seq_all = bufs.get("fin_off"), bufs.get("fin_seq")
+
+    def route_off(self, k):
+        return self.off_all[int(self.off_start[k]):int(self.off_start[k + 1])]
+
+    def route_seq(self, k):
+        return self.seq_all[int(self.seq_start[k]):int(self.seq_start[k + 1])]
+
+    def route_of(self, k):
+        return self.of_all[int(self.seq_start[k]):int(self.seq_start[k + 1])]
+
+    def final_off(self, k):
+        return self.fin_off_all[int(self.off_start[k]):int(self.off_start[k + 1])]
+
+    def final_seq(self, k):
+        return self.fin_seq_all[int(self.seq_start[k]):int(self.seq_start[k + 1])]
+
+
+def _result_dtype():
+    names = [f[0] for f in _Result._fields_]
+    kinds = {C.c_void_p: np.uint64, C.c_int64: np.int64, C.c_int32: np.int32, C.c_float: np.float32}
+    return np.dtype({"names": names, "formats": [kinds[f[1]] for f in _Result._fields_],
+                     "offsets": [getattr(_Result, n).offset for n in names],
+                     "itemsize": C.sizeof(_Result)})
+
+
+def solve_batch_flat(insts, params, n_restarts=1, ws=None, stream=None, final_routes=False,
+                     allow_infeasible=False, bufs=None):
+    """n instances x n_restarts solves in one call (at_solve_batch) without a
+    trace, the result descriptors built as one numpy array: the marshalling of a
+    batch of tens of thousands of solves costs milliseconds.  `bufs` (the
+    BatchResult of an earlier call on the same instances and restart count)
+    reuses its output tensors.  Returns a BatchResult."""
+    torch = _torch()
+    n = len(insts)
+    ia = (_Instance * n)(*[i.c_struct() for i in insts])
+    pa = (_Params * n)(*params)
+    if any(p.trace for p in params):
+        raise AtError(AT_EINVAL, "solve_batch_flat writes no trace")
+    nbytes = int(lib().at_workspace_size(n, ia, pa, n_restarts))
+    if nbytes == 0:
+        _check(AT_EINVAL)
+    ws = _workspace(nbytes, ws)
+    V = np.repeat(np.array([i.n_vehicles for i in insts], dtype=np.int64), n_restarts)
+    M = np.repeat(np.array([i.n_missions for i in insts], dtype=np.int64), n_restarts)
+    off_start = np.concatenate([[0], np.cumsum(V + 1)])
+    seq_start = np.concatenate([[0], np.cumsum(M)])
+    dev = insts[0].travel.device
+    if bufs is not None:
+        b = dict(off=bufs.off_all, seq=bufs.seq_all, of=bufs.of_all)
+        if final_routes:
+            b.update(fin_off=bufs.fin_off_all, fin_seq=bufs.fin_seq_all)
+    else:
+        b = dict(off=torch.empty(int(off_start[-1]), dtype=torch.int32, device=dev),
+                 seq=torch.empty(max(1, int(seq_start[-1])), dtype=torch.int32, device=dev),
+                 of=torch.empty(max(1, int(seq_start[-1])), dtype=torch.int32, device=dev))
+        if final_routes:
+            b.update(fin_off=torch.empty_like(b["off"]), fin_seq=torch.empty_like(b["seq"]))
+    k = len(V)
+    ra = np.zeros(k, dtype=_result_dtype())
+    ra["route_off"] = b["off"].data_ptr() + 4 * off_start[:-1].astype(np.uint64)
+    ra["route_seq"] = b["seq"].data_ptr() + 4 * seq_start[:-1].astype(np.uint64)
+    ra["route_of"] = b["of"].data_ptr() + 4 * seq_start[:-1].astype(np.uint64)
+    if final_routes:
+        ra["final_off"] = b["fin_off"].data_ptr() + 4 * off_start[:-1].astype(np.uint64)
+        ra["final_seq"] = b["fin_seq"].data_ptr() + 4 * seq_start[:-1].astype(np.uint64)
+    rc = lib().at_solve_batch(n, ia, pa, n_restarts, _dptr(ws), ws.numel(), _stream_ptr(stream),
+                              ra.ctypes.data_as(C.POINTER(_Result)))
+    if not (allow_infeasible and rc == AT_EINFEAS):
+        _check(rc)
+    out = BatchResult(k, off_start, seq_start, b)
+    for f in ("best_obj", "final_obj", "iters_done", "best_iter", "status", "search_ms"):
+        setattr(out, f, ra[f].copy())
+    return out
+
+
 def debug_eval_moves(inst: DeviceInstance, route_off, route_seq, tabu_until, t, cur, best,
                      variant=AT_TABU, aspiration=True, chunk=0, block=0, schedule=SCHED_AUTO,
                      ws=None, stream=None):

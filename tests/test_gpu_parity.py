@@ -395,3 +395,23 @@ def test_global_shared_launch_partition():
         alone = at.solve(d, tenure=5, iters=40, schedule=at.SCHED_GLOBAL, n_groups=3)
         assert np.array_equal(gpu_to_np(res[k])["tr_move"], gpu_to_np(alone)["tr_move"]), k
         assert res[k]["best_obj"] == alone["best_obj"], k
+
+
+def test_flat_batch_marshalling_equals_list():
+    """solve_batch_flat (descriptors built as one numpy array, routes in flat
+    tensors) gives the same results as solve_batch on the same batch."""
+    specs = batch_specs(24)
+    devs = [_dev(batch_instance(dict(s, iters=120))) for s in specs]
+    params = [at._capi.make_params(at.AT_TABU, s["tenure"], 120, True, s["seed"], False) for s in specs]
+    lst = at.solve_batch(devs, params, 3)
+    flat = at.solve_batch_flat(devs, params, 3, final_routes=True)
+    assert flat.n == len(lst)
+    for k, r in enumerate(lst):
+        r = gpu_to_np(r)
+        for f in ("best_obj", "final_obj", "iters_done", "best_iter", "status"):
+            assert getattr(flat, f)[k] == r[f], (k, f)
+        assert np.array_equal(flat.route_off(k).cpu().numpy(), r["route_off"])
+        assert np.array_equal(flat.route_seq(k).cpu().numpy(), r["route_seq"])
+        assert np.array_equal(flat.route_of(k).cpu().numpy(), r["route_of"])
+        assert np.array_equal(flat.final_off(k).cpu().numpy(), r["final_off"])
+        assert np.array_equal(flat.final_seq(k).cpu().numpy(), r["final_seq"])
