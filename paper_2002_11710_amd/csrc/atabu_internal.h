@@ -296,4 +296,40 @@ int num_cus();
 hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Wavefront minimum on the VALU's data-parallel primitives (DPP): each step is
+// one v_min_u32 whose second operand comes from another lane of the row (quad
+// swaps, the half-row and row mirrors) or, for rows 1 and 3 and then rows 2
+// and 3, from the last lane of the row before (row broadcasts 15 and 31), so
+// lane 63 ends with the minimum of all 64 lanes, read out as a wave-uniform
+// value.  Lanes a step does not write keep their value (the old operand is the
+// identity).  The 64-bit form takes the minimum of the high words, then of the
+// low words among the lanes that hold it.  Every lane of the wavefront must be
+// active.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x)
+{
+    const uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)x, CTRL, ROWS, 0xF, false);
+    return x < y ? x : y;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
+{
+    x = dpp_min_step<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+    x = dpp_min_step<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+    x = dpp_min_step<0x141, 0xF>(x);   // row_half_mirror
+    x = dpp_min_step<0x140, 0xF>(x);   // row_mirror
+    x = dpp_min_step<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+    x = dpp_min_step<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t k)
+{
+    const uint32_t hi = wave_min_u32((uint32_t)(k >> 32));
+    const uint32_t lo = wave_min_u32((uint32_t)(k >> 32) == hi ? (uint32_t)k : 0xFFFFFFFFu);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 }  // namespace at

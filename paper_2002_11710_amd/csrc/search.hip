@@ -115,17 +115,7 @@ __device__ __forceinline__ uint4 gld16(uint64_t addr, int o)
     return make_uint4(x.x, x.y, x.z, x.w);
 }
 
-__device__ __forceinline__ uint64_t wave_min(uint64_t k)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)k, o, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(k >> 32), o, 64);
-        const uint64_t x = ((uint64_t)hi << 32) | lo;
-        k = x < k ? x : k;
-    }
-    return k;
-}
+__device__ __forceinline__ uint64_t wave_min(uint64_t k) { return wave_min_u64(k); }
 
 __device__ __forceinline__ uint64_t pack_key(bool blocked, int delta, uint32_t idx)
 {
@@ -676,6 +666,190 @@ __device__ int64_t greedy(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc
     index_routes(c, tid, nthr);
     const int64_t acc = (int64_t)c.red[100];
     bsync<WAVE>();
+    return acc + svc_sum;
+}
+
+// The missions' steps of greedy_staged with the per-vehicle state in registers:
+// lane l holds vehicles l, l + 64, ... (VPL of them, V <= 64 VPL) with their
+// route end, return leg and count, so a step is one round of travel gathers
+// (all of a lane's issued together), one wavefront minimum and the winner's
+// lane updating its own registers; the next mission's row and column are read
+// a step ahead.  Writes each step's vehicle and rank, and each vehicle's count;
+// returns the sum of the added times.  M >= 1.
+template <typename TE, int VPL>
+__device__ int64_t greedy_steps_regs(const Ctx &c, const TE *tc, bool seeded, const int32_t *pi,
+                                     int32_t *cnt, uint16_t *veh, uint16_t *rnk, int lane)
+{
+    const int M = c.M, V = c.V;
+    const auto g = [](const TE *p, int k) { return (int)gld(p)[k]; };
+    int lx[VPL], vc[VPL], ec[VPL], n[VPL];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) {
+        // lanes past the fleet read the last vehicle and never take part
+        const int v = min(lane + j * kWave, V - 1);
+        lx[j] = gld(c.vrow)[v];
+        vc[j] = gld(c.vcol)[v];
+        n[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) ec[j] = g(tc, lx[j] + vc[j]);
+    int64_t acc = 0;
+    int mn = seeded ? pi[0] : 0;
+    int mcn = gld(c.mcol)[mn], mrn = gld(c.mrow)[mn];
+    for (int s = 0; s < M; ++s) {
+        const int mc = mcn, mr = mrn;
+        if (s + 1 < M) {
+            mn = seeded ? pi[s + 1] : s + 1;
+            mcn = gld(c.mcol)[mn];
+            mrn = gld(c.mrow)[mn];
+        }
+        int a[VPL], r[VPL];
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+            a[j] = g(tc, lx[j] + mc);
+            r[j] = g(tc, mr + vc[j]);
+        }
+        uint64_t k = kKeyNone;
+        int kj = 0;
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+            const int v = lane + j * kWave;
+            const uint64_t kv = v < V ? ((uint64_t)(uint32_t)(a[j] + r[j] - ec[j] + kDeltaBias) << 32) | (uint32_t)v
+                                      : kKeyNone;
+            if (kv < k) { k = kv; kj = j; }
+        }
+        const uint64_t kw = wave_min(k);
+        acc += (int64_t)(int32_t)(uint32_t)(kw >> 32) - kDeltaBias;
+        if (kw == k) {   // the winner's lane (keys are unique: they hold the vehicle)
+            int rank = 0;
+#pragma unroll
+            for (int j = 0; j < VPL; ++j)
+                if (j == kj) {
+                    rank = n[j];
+                    n[j] = rank + 1;
+                    lx[j] = mr;
+                    ec[j] = r[j];   // the return leg after the new last mission
+                }
+            veh[s] = (uint16_t)(uint32_t)kw;
+            rnk[s] = (uint16_t)rank;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < VPL; ++j)
+        if (lane + j * kWave < V) cnt[lane + j * kWave] = n[j];
+    return acc;
+}
+
+// Algorithm 1 as greedy() computes it, for the HBM-resident schedule: the
+// per-mission results (vehicle, rank within the vehicle) live in the
+// workgroup's LDS `lds` (at least greedy_staged_bytes), and so does the
+// per-vehicle state (route end, return leg, count) beyond 256 vehicles (up to
+// 256 it stays in registers: greedy_steps_regs), so each mission's step waits
+// only for its travel gathers from HBM (one round of them: the next mission's
+// row and column are read a step ahead; the winner's new return leg is the
+// gather its lane already made); the routes are then written by all threads at
+// once, each mission at its vehicle's offset plus its rank.  Returns the
+// objective.
+__host__ __device__ inline uint32_t greedy_staged_bytes(int M, int V, bool seeded)
+{
+    return 16u * (uint32_t)V + 4u * (uint32_t)M + (seeded ? 8u * (uint32_t)M : 0u) + 64u;
+}
+
+template <typename TE>
+__device__ int64_t greedy_staged(const Ctx &c, const TE *tc, uint64_t seed, int64_t svc_sum, char *lds,
+                                 int tid, int nthr)
+{
+    const int M = c.M, V = c.V;
+    int32_t *lastx = (int32_t *)lds, *endc = lastx + V, *cnt = endc + V, *vcl = cnt + V;
+    uint16_t *veh = (uint16_t *)(vcl + V), *rnk = veh + M;
+    int32_t *pi = (int32_t *)(rnk + M + (M & 1)), *drw = pi + M;     // seeded only
+    int64_t *acc_out = (int64_t *)c.red;
+    const auto g = [](const TE *p, int k) { return (int)gld(p)[k]; };
+    for (int v = tid; v < V; v += nthr) {
+        const int x = gld(c.vrow)[v], vc = gld(c.vcol)[v];
+        lastx[v] = x;
+        vcl[v] = vc;
+        endc[v] = g(tc, x + vc);
+        cnt[v] = 0;
+    }
+    if (seed != 0)
+        for (int i = tid; i < M; i += nthr) {
+            pi[i] = i;
+            if (i >= 1) drw[i] = (int32_t)(splitmix_at(seed, (uint64_t)(M - i)) % (uint64_t)(i + 1));
+        }
+    __syncthreads();
+    if (seed != 0 && tid == 0)
+        for (int i = M - 1; i >= 1; --i) {
+            const int j = drw[i];
+            const int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
+        }
+    __syncthreads();
+    if (tid < kWave && M > 0 && V <= 4 * kWave) {
+        const int lane = tid;
+        int64_t acc;
+        if (V <= kWave) acc = greedy_steps_regs<TE, 1>(c, tc, seed != 0, pi, cnt, veh, rnk, lane);
+        else if (V <= 2 * kWave) acc = greedy_steps_regs<TE, 2>(c, tc, seed != 0, pi, cnt, veh, rnk, lane);
+        else acc = greedy_steps_regs<TE, 4>(c, tc, seed != 0, pi, cnt, veh, rnk, lane);
+        if (lane == 0) acc_out[100] = acc;
+    } else if (tid < kWave) {
+        const int lane = tid;
+        int64_t acc = 0;
+        int mn = M > 0 ? (seed ? pi[0] : 0) : 0;
+        int mcn = M > 0 ? gld(c.mcol)[mn] : 0, mrn = M > 0 ? gld(c.mrow)[mn] : 0;
+        for (int s = 0; s < M; ++s) {
+            const int mc = mcn, mr = mrn;
+            if (s + 1 < M) {
+                mn = seed ? pi[s + 1] : s + 1;
+                mcn = gld(c.mcol)[mn];
+                mrn = gld(c.mrow)[mn];
+            }
+            // each lane keeps the return leg of its own best vehicle: the winner's
+            // lane then has the new route end without another gather
+            uint64_t k = kKeyNone;
+            int kret = 0;
+            for (int v = lane; v < V; v += kWave) {
+                const int x = lastx[v], vc = vcl[v];
+                const int ret = g(tc, mr + vc);
+                const int add = g(tc, x + mc) + ret - endc[v];
+                const uint64_t kv = ((uint64_t)(uint32_t)(add + kDeltaBias) << 32) | (uint32_t)v;
+                if (kv < k) { k = kv; kret = ret; }
+            }
+            const uint64_t kw = wave_min(k);
+            const int vs = (int)(uint32_t)kw;
+            acc += (int64_t)(int32_t)(uint32_t)(kw >> 32) - kDeltaBias;
+            if (kw == k) {   // the winner's lane (keys are unique: they hold the vehicle)
+                const int r = cnt[vs];
+                endc[vs] = kret;
+                lastx[vs] = mr;
+                cnt[vs] = r + 1;
+                veh[s] = (uint16_t)vs;
+                rnk[s] = (uint16_t)r;
+            }
+            bsync<true>();
+        }
+        if (lane == 0) acc_out[100] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int o = 0;
+        for (int v = 0; v < V; ++v) {
+            const int n = cnt[v];
+            cnt[v] = o;
+            gst(c.off)[v] = o;
+            o += n;
+        }
+        gst(c.off)[V] = o;
+    }
+    __syncthreads();
+    for (int s2 = tid; s2 < M; s2 += nthr) {
+        const int v = veh[s2], m = seed ? pi[s2] : s2, q = cnt[v] + rnk[s2];
+        gst(c.seq)[q] = (uint16_t)m;
+        gst(c.rt)[q] = (uint16_t)v;
+        gst(c.pof)[m] = (uint16_t)q;
+        gst(c.rof)[m] = (uint16_t)v;
+    }
+    const int64_t acc = acc_out[100];
+    __syncthreads();
     return acc + svc_sum;
 }
 
@@ -1516,7 +1690,10 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
         p = 0;
         if (wg == 0) {
             const Ctx c0 = global_ctx(I, B, 0, red);
-            const int64_t g = greedy<TE>(c0, tc, J.seed, I.svc_sum, tid, nthr);
+            const uint32_t lds = global_lds_bytes(J.gk, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
+            const int64_t g = greedy_staged_bytes(M, V, J.seed != 0) + 2048u <= lds
+                                  ? greedy_staged<TE>(c0, tc, J.seed, I.svc_sum, smem, tid, nthr)
+                                  : greedy<TE>(c0, tc, J.seed, I.svc_sum, tid, nthr);
             if (tid == 0) __hip_atomic_store(&B.init_obj, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             snapshot(c0, J, tid, nthr);
         }

@@ -42,17 +42,7 @@ namespace {
 constexpr uint64_t kG = 0x9E3779B97F4A7C15ull;
 constexpr int32_t kBig = 0x3FFFFFFF;   // an unreachable time (no limit)
 
-__device__ __forceinline__ uint64_t wmin(uint64_t k)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)k, o, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(k >> 32), o, 64);
-        const uint64_t x = ((uint64_t)hi << 32) | lo;
-        k = x < k ? x : k;
-    }
-    return k;
-}
+__device__ __forceinline__ uint64_t wmin(uint64_t k) { return wave_min_u64(k); }
 
 // all lanes' LDS writes before this point are seen by all lanes' reads after it
 __device__ __forceinline__ void wsync()

@@ -357,6 +357,20 @@ def test_global_schedule_tenure_edges(tenure, iters):
         assert_same_result(o, g, f"global tenure {tenure} iters {iters} variant {variant}")
 
 
+@pytest.mark.parametrize("vehicles,seed,groups", [(16, 0, 4), (16, 5, 4), (16, 9, 1), (16, 3, 16),
+                                                   (100, 0, 8), (100, 7, 8), (300, 0, 8), (300, 11, 2)])
+def test_global_schedule_greedy_orders(vehicles, seed, groups):
+    """The HBM-resident schedule's greedy start (per-vehicle state in registers up
+    to 64, 128 and 256 vehicles, in LDS beyond) with the identity and seeded
+    orders, at group counts that change its LDS budget: the oracle's whole
+    trajectory from that start."""
+    inst = m400_instance(0) if vehicles == 16 else make_instance(40 + vehicles, 150, 12, vehicles, 400)
+    _, o = oracle_solve(inst, tenure=15, iters=60, restart_seed=seed)
+    g = at.solve(_dev(inst), tenure=15, iters=60, restart_seed=seed, schedule=at.SCHED_GLOBAL,
+                 n_groups=groups)
+    assert_same_result(o, g, f"global greedy seed {seed} groups {groups}")
+
+
 def test_stress_instance_prefix():
     """The 256-vehicle x 10000-mission instance: greedy start and the first
     iterations against the oracle (each oracle iteration scores 1.5e8 moves)."""
