@@ -608,14 +608,13 @@ def bench_serve_sweep(rates, n_req: int, chunk: int = 50, slots: int = 256, budg
                                    trace=False)] = submitted
                 submitted += 1
             srv.progress()
-            for tk in list(tickets):
+            for tk in srv.completed():
                 r = srv.poll(tk)
-                if r is not None:
-                    k = tickets.pop(tk)
-                    assert r["status"] == 0
-                    done[k] = time.perf_counter() - t0
-                    if k < plain:
-                        res[k] = (int(r["best_obj"]), r["route_seq"].cpu())
+                k = tickets.pop(tk)
+                assert r is not None and r["status"] == 0
+                done[k] = time.perf_counter() - t0
+                if k < plain:
+                    res[k] = (int(r["best_obj"]), r["route_seq"].cpu())
             if not tickets and submitted < n_req:
                 time.sleep(max(0.0, min(0.001, arrivals[submitted] - (time.perf_counter() - t0))))
         wall = time.perf_counter() - t0

@@ -263,11 +263,18 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params,
  * iteration, S < 2^20, runs floor(2^20 / S) times as many, up to the rest of
  * its budget), so requests that arrive while others run start within one
  * chunk.  Each request's result is the same as at_solve's.
+ * `stream` is the caller's: requests are admitted (their instance arrays read)
+ * and results copied out on it; the solves themselves run on an internal
+ * stream of default priority, so a poll never waits for the launch in flight.
  * at_server_submit returns a ticket; the instance's device arrays are read
  * when the request is admitted, so the caller keeps them valid until
  * at_server_poll has returned the result;
  * at_server_poll returns AT_OK with the result when done (out's arrays are
- * device memory of the caller, filled then), AT_EAGAIN while pending;
+ * device memory of the caller, filled on `stream` and complete on return),
+ * AT_EAGAIN while pending;
+ * at_server_completed writes up to `capacity` tickets of requests that are
+ * done and not yet polled, each once, in the order they finished (*n_out of
+ * them), so a caller polls only those;
  * at_server_progress drives the device (call it from one thread, in a loop);
  * at_server_destroy waits for running work and frees everything. */
 int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_iters,
@@ -276,6 +283,7 @@ int at_server_submit(void *server, const at_instance *inst, const at_params *par
                      uint64_t *ticket);
 int at_server_progress(void *server, int32_t *n_active);
 int at_server_poll(void *server, uint64_t ticket, at_result *out);
+int at_server_completed(void *server, uint64_t *tickets, int32_t capacity, int32_t *n_out);
 int at_server_destroy(void *server);
 
 /* Release what the library holds between calls: the internal streams on

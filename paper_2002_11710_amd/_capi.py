@@ -17,7 +17,7 @@ lib_path = os.path.join(_HERE, "libatabu.so")
 
 _EXPORTS = ("at_build_travel", "at_build_travel_device", "at_workspace_size", "at_solve",
             "at_solve_noalloc", "at_solve_batch", "at_debug_eval_moves", "at_server_create", "at_server_submit",
-            "at_server_progress", "at_server_poll", "at_server_destroy", "at_shutdown",
+            "at_server_progress", "at_server_poll", "at_server_completed", "at_server_destroy", "at_shutdown",
             "at_last_error")
 
 
@@ -85,6 +85,7 @@ def lib():
                                                C.POINTER(u64)]
                 L.at_server_progress.argtypes = [vp, C.POINTER(i32)]
                 L.at_server_poll.argtypes = [vp, u64, C.POINTER(_Result)]
+                L.at_server_completed.argtypes = [vp, C.POINTER(u64), i32, C.POINTER(i32)]
                 L.at_server_destroy.argtypes = [vp]
             _lib = L
     return _lib
@@ -475,6 +476,13 @@ class Server:
         _check(rc)
         del self._pending[ticket]
         return _finish(bufs, res, M)
+
+    def completed(self, capacity: int = 4096):
+        """Tickets of requests that finished since the last call (at_server_completed)."""
+        buf = (C.c_uint64 * capacity)()
+        n = C.c_int32(0)
+        _check(lib().at_server_completed(self._h, buf, int(capacity), C.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
 
     def close(self):
         if self._h:

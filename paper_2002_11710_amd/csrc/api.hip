@@ -491,8 +491,10 @@ int release_class_streams()
 // streams.  Then, in order on the caller's stream: one cooperative launch per
 // group of HBM-resident jobs that assign_groups put together (each job on its
 // own range of the grid), and one cooperative launch per multi-workgroup job.
+// With wg_workers > 0 the two first kinds can instead share one grid (see
+// engine.h).
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
-                Xchg *xs, hipStream_t s)
+                Xchg *xs, hipStream_t s, int wg_workers)
 {
     hipError_t e;
     const int n = (int)order.size();
@@ -515,16 +517,62 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         k = c.k1;
     }
     if ((int)cls.size() > kMaxClasses) return fail(AT_EINVAL, "too many launch classes");
+    // the HBM-resident launches of the global jobs that assign_groups put together,
+    // in order on stream `st`
+    auto launch_globals = [&](int k0, hipStream_t st) -> int {
+        for (int q = k0; q < n;) {
+            const JobHost &hf = jobs[(size_t)order[(size_t)q]];
+            if (hf.kind != AT_SCHED_GLOBAL) return fail(AT_EINVAL, "job order: a global job after the others expected");
+            int e1 = q, groups = 0;
+            uint32_t lds = 0;
+            while (e1 < n && jobs[(size_t)order[(size_t)e1]].kind == AT_SCHED_GLOBAL &&
+                   jobs[(size_t)order[(size_t)e1]].launch == hf.launch) {
+                const JobHost &h = jobs[(size_t)order[(size_t)e1]];
+                groups = std::max(groups, h.g0 + h.groups);
+                lds = std::max(lds, h.lds);
+                ++e1;
+            }
+            hipError_t e2 = launch_search_global(dj + q, e1 - q, groups, hf.block, lds, hf.tb16, hf.esz16, st);
+            if (e2 != hipSuccess) return hip_fail(e2, "search launch (HBM-resident schedule)");
+            q = e1;
+        }
+        return AT_OK;
+    };
+    // Both kinds present, the one-workgroup jobs of the global jobs' entry and tabu
+    // widths and the global jobs in one launch: one grid runs them all, wg_workers
+    // workgroups taking the one-workgroup jobs from the queue (k_search_mixed).
+    if (wg_workers > 0 && !cls.empty() && k < n) {
+        const JobHost &g0 = jobs[(size_t)order[(size_t)k]];
+        bool fuse = true;
+        uint32_t lds = 0;
+        int n_ggroups = 0;
+        for (int q = 0; q < n && fuse; ++q) {
+            const JobHost &h = jobs[(size_t)order[(size_t)q]];
+            const bool global = q >= k;
+            if (h.esz16 != g0.esz16 || h.tb16 != g0.tb16) fuse = false;
+            if (global && (h.kind != AT_SCHED_GLOBAL || h.launch != g0.launch || h.block != kGlobalBlock)) fuse = false;
+            if (!global && (h.kind != AT_SCHED_WG || h.wtile)) fuse = false;
+            lds = std::max(lds, h.lds);
+            if (global) n_ggroups = std::max(n_ggroups, h.g0 + h.groups);
+        }
+        if (fuse) {
+            if ((e = fill_u32(xs->queues, 0u, 1, s)) != hipSuccess) return hip_fail(e, "reset queue");
+            e = launch_search_mixed(dj + k, n - k, n_ggroups, dj, k, &xs->queues[0], wg_workers, lds, g0.tb16,
+                                    g0.esz16, s);
+            return e == hipSuccess ? AT_OK : hip_fail(e, "search launch (both schedules)");
+        }
+    }
     if (!cls.empty()) {
         if ((e = fill_u32(xs->queues, 0u, kMaxClasses, s)) != hipSuccess) return hip_fail(e, "reset queues");
         hipEvent_t fork = nullptr;
         std::vector<hipEvent_t> joins(cls.size(), nullptr);
         const bool split = cls.size() > 1;
-        if (split) {
-            if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-            if ((e = hipEventRecord(fork, s)) != hipSuccess) return hip_fail(e, "event");
-        }
         int rc = AT_OK;
+        if (split) {
+            if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventRecord(fork, s)) != hipSuccess)
+                rc = hip_fail(e, "event");
+        }
         for (size_t c = 0; c < cls.size() && rc == AT_OK; ++c) {
             const Cls &q = cls[c];
             hipStream_t st = s;
@@ -572,20 +620,8 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
     while (k < n) {
         const JobHost &hf = jobs[(size_t)order[(size_t)k]];
         if (hf.kind == AT_SCHED_GLOBAL) {
-            // one cooperative launch for the jobs assign_groups put together
-            int e1 = k, groups = 0;
-            uint32_t lds = 0;
-            while (e1 < n && jobs[(size_t)order[(size_t)e1]].kind == AT_SCHED_GLOBAL &&
-                   jobs[(size_t)order[(size_t)e1]].launch == hf.launch) {
-                const JobHost &h = jobs[(size_t)order[(size_t)e1]];
-                groups = std::max(groups, h.g0 + h.groups);
-                lds = std::max(lds, h.lds);
-                ++e1;
-            }
-            if ((e = launch_search_global(dj + k, e1 - k, groups, hf.block, lds, hf.tb16, hf.esz16, s)) != hipSuccess)
-                return hip_fail(e, "cooperative search launch");
-            k = e1;
-            continue;
+            // the global jobs, which come last: one cooperative launch per group of them
+            return launch_globals(k, s);
         }
         if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups * kSlotStride, s)) != hipSuccess)
             return hip_fail(e, "reset exchange");
@@ -624,7 +660,7 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
 // into cooperative launches and give each job a range of its launch's
 // workgroups: as many as it asked for when they all fit the co-resident
 // limit, else shares proportional to the request (at least one each).
-int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
+int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order, int max_groups)
 {
     const int n = (int)order.size();
     int k = 0, launch = 0;
@@ -639,7 +675,8 @@ int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
             lds = std::max(lds, h.lds);
             ++e;
         }
-        const int cap = max_groups_global(hf.block, lds, hf.tb16, hf.esz16);
+        int cap = max_groups_global(hf.block, lds, hf.tb16, hf.esz16);
+        if (max_groups > 0) cap = std::min(cap, max_groups);
         if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
         for (int a = k; a < e; a += cap, ++launch) {
             const int b = std::min(e, a + cap);

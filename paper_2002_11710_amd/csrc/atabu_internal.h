@@ -244,6 +244,12 @@ hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int bl
 hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
+// One grid for both kinds (block kGlobalBlock): n_ggroups workgroups for the
+// global jobs, n_workers taking one-workgroup jobs from queue[0]; cooperative.
+hipError_t launch_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups, const JobDev *wjobs, int n_wjobs,
+                               uint32_t *queue, int n_workers, uint32_t lds_bytes, int tb16, int esz16,
+                               hipStream_t s);
+int max_groups_mixed(uint32_t lds_bytes, int tb16, int esz16);
 // Missions staged per block by the global schedule's eval, at most.
 constexpr int kGlobalKMax = 64;
 static_assert(kGlobalKMax <= kWave, "a block's missions fit one wavefront");

@@ -29,6 +29,9 @@
 // index order for a fixed lane: the gap offset for relocates, the partner's
 // mission id for swaps (ranked inside the chunk by prep), so ties resolve to
 // the smallest slot index exactly as the full 64-bit comparison would.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "atabu_internal.h"
@@ -1831,10 +1834,8 @@ __device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uin
 // At most kGlobalBlock threads per workgroup: the register budget that leaves
 // (256 VGPRs) keeps the per-iteration state out of scratch memory.
 template <typename TE, typename TB>
-__global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jobs, int n_jobs)
+__device__ __forceinline__ void global_group(const JobDev *jobs, int n_jobs, int b, char *smem)
 {
-    extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int b = (int)blockIdx.x;
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1845,6 +1846,42 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jo
     const uint32_t lds = global_lds_bytes(J.gk, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
     uint64_t *red = (uint64_t *)(smem + lds - 2048);
     run_job_global<TE, TB>(J, b - J.g0, J.ng, smem, red);
+}
+
+template <typename TE, typename TB>
+__global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jobs, int n_jobs)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    global_group<TE, TB>(jobs, n_jobs, (int)blockIdx.x, smem);
+}
+
+// One-workgroup jobs and HBM-resident jobs of one launch in one grid:
+// workgroups [0, n_ggroups) run the global jobs as k_search_global does, the
+// others take one-workgroup jobs from the queue as k_search_wg does (with this
+// kernel's block size).  The two kinds share the device inside one
+// cooperative launch, so every workgroup is resident and nothing waits for
+// another stream.  A worker passes the job index through the first word of
+// its LDS between two barriers, before the job's own use of it.
+template <typename TE, typename TB>
+__global__ void __launch_bounds__(kGlobalBlock) k_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups,
+                                                              const JobDev *wjobs, int n_wjobs, uint32_t *queue)
+{
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    if ((int)blockIdx.x < n_ggroups) {
+        global_group<TE, TB>(gjobs, n_gjobs, (int)blockIdx.x, smem);
+        return;
+    }
+    int *s_job = (int *)smem;
+    for (;;) {
+        if (threadIdx.x == 0)
+            *s_job = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int j = *s_job;
+        __syncthreads();
+        if (j >= n_wjobs) return;
+        run_job<TE, TB, false>(wjobs[j], smem, 0, 1, nullptr);
+        __syncthreads();
+    }
 }
 
 // Reset the exchange state of every solve of a global-schedule launch (one
@@ -2043,13 +2080,75 @@ hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, in
 }
 
 template <typename TE, typename TB>
+static hipError_t coop_launch_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups, const JobDev *wjobs,
+                                    int n_wjobs, uint32_t *queue, int n_workers, uint32_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = set_lds(k_search_mixed<TE, TB>, lds_bytes);
+    if (e != hipSuccess) return e;
+    void *args[] = {(void *)&gjobs, (void *)&n_gjobs, (void *)&n_ggroups, (void *)&wjobs, (void *)&n_wjobs,
+                    (void *)&queue};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search_mixed<TE, TB>),
+                                      dim3(n_ggroups + n_workers), dim3(kGlobalBlock), args, lds_bytes, s);
+}
+
+hipError_t launch_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups, const JobDev *wjobs, int n_wjobs,
+                               uint32_t *queue, int n_workers, uint32_t lds_bytes, int tb16, int esz16,
+                               hipStream_t s)
+{
+    k_reset_global<<<dim3((unsigned)n_gjobs), dim3(256), 0, s>>>(gjobs, n_gjobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define AT_MX(TE, TB) \
+    return coop_launch_mixed<TE, TB>(gjobs, n_gjobs, n_ggroups, wjobs, n_wjobs, queue, n_workers, lds_bytes, s)
+    if (esz16 && tb16) AT_MX(uint16_t, uint16_t);
+    if (esz16) AT_MX(uint16_t, int32_t);
+    if (tb16) AT_MX(int32_t, uint16_t);
+    AT_MX(int32_t, int32_t);
+#undef AT_MX
+}
+
+template <typename TE, typename TB>
+static int occupancy_mixed(uint32_t lds_bytes)
+{
+    if (set_lds(k_search_mixed<TE, TB>, lds_bytes) != hipSuccess) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_mixed<TE, TB>, kGlobalBlock,
+                                                     lds_bytes) != hipSuccess)
+        return 0;
+    return per_cu * num_cus();
+}
+
+int max_groups_mixed(uint32_t lds_bytes, int tb16, int esz16)
+{
+    if (esz16 && tb16) return occupancy_mixed<uint16_t, uint16_t>(lds_bytes);
+    if (esz16) return occupancy_mixed<uint16_t, int32_t>(lds_bytes);
+    if (tb16) return occupancy_mixed<int32_t, uint16_t>(lds_bytes);
+    return occupancy_mixed<int32_t, int32_t>(lds_bytes);
+}
+
+// Workgroups of the global schedule one CU holds, per (entry width, tabu width,
+// block size, LDS bytes), asked of the runtime once per device and key.
+static std::mutex g_occ_mu;
+static std::map<std::tuple<int, int, int, int, uint32_t>, int> g_occ;
+
+template <typename TE, typename TB>
 static int occupancy_global(int block, uint32_t lds_bytes)
 {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    const auto key = std::make_tuple(dev, (int)sizeof(TE), (int)sizeof(TB), block, lds_bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        auto it = g_occ.find(key);
+        if (it != g_occ.end()) return it->second * num_cus();
+    }
     if (set_lds(k_search_global<TE, TB>, lds_bytes) != hipSuccess) return 0;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_global<TE, TB>, block,
                                                      lds_bytes) != hipSuccess)
         return 0;
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    g_occ[key] = per_cu;
     return per_cu * num_cus();
 }
 

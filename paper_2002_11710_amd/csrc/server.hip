@@ -12,6 +12,7 @@
 // solve is deterministic and resumes exactly where it stopped, its result does
 // not depend on what else is resident or on the chunking.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -139,8 +140,15 @@ struct Server {
     std::vector<JobScal> hscal;
     std::vector<int> free_slots;
     hipEvent_t done_ev = nullptr;
+    // The solves run on an internal stream: admission (reading the caller's
+    // instance arrays) and result copies stay on the caller's stream `s`, so a
+    // poll never waits for the launch in flight.  adm_ev marks the end of the
+    // last admission's uploads, which the next launch waits for.
+    hipStream_t ls = nullptr;
+    hipEvent_t adm_ev = nullptr;
     bool in_flight = false;
     uint64_t next_ticket = 1;
+    std::deque<uint64_t> finished;    // tickets done and not yet listed by at_server_completed
     std::deque<Request *> waiting;
     std::vector<Request *> active;
     std::map<uint64_t, Request *> all;
@@ -155,6 +163,11 @@ struct Server {
     ~Server()
     {
         if (in_flight && done_ev) (void)hipEventSynchronize(done_ev);
+        if (ls) {
+            (void)hipStreamSynchronize(ls);
+            (void)hipStreamDestroy(ls);
+        }
+        if (adm_ev) (void)hipEventDestroy(adm_ev);
         for (auto &kv : all) delete kv.second;
         if (done_ev) (void)hipEventDestroy(done_ev);
         if (hstage) (void)hipHostFree(hstage);
@@ -268,6 +281,8 @@ struct Server {
             k_scatter<<<dim3(ne), dim3(256), 0, s>>>(dscat, dstage);
             if ((e = hipGetLastError()) != hipSuccess) src = hip_fail(e, "server: admission scatter");
         }
+        // the next launch (on the internal stream) waits for these uploads
+        if (src == AT_OK && (e = hipEventRecord(adm_ev, s)) != hipSuccess) src = hip_fail(e, "server: admission event");
         for (Request *r : cand) {
             if (src != AT_OK) {
                 finish_failed(*r, src);
@@ -284,6 +299,7 @@ struct Server {
     void finish_failed(Request &r, int status)
     {
         r.done = true;
+        finished.push_back(r.ticket);
         r.last.status = status;
         arena.release(r.mem, r.bytes);
         r.mem = nullptr;
@@ -295,9 +311,9 @@ struct Server {
     int collect()
     {
         if (active.empty()) return AT_OK;
-        hipError_t e = hipMemcpyAsync(hscal.data(), dscal, sizeof(JobScal) * hscal.size(), hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(hscal.data(), dscal, sizeof(JobScal) * hscal.size(), hipMemcpyDeviceToHost, ls);
         if (e != hipSuccess) return hip_fail(e, "server: read back");
-        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "server: chunk");
+        if ((e = hipStreamSynchronize(ls)) != hipSuccess) return hip_fail(e, "server: chunk");
         std::vector<Request *> keep;
         for (Request *r : active) {
             const JobScal &h = hscal[(size_t)r->slot];
@@ -305,6 +321,7 @@ struct Server {
             r->t = h.iters_done;
             if (h.status != AT_OK || h.stopped || r->t >= r->pr.max_iters) {
                 r->done = true;
+                finished.push_back(r->ticket);
                 free_slots.push_back(r->slot);
                 r->slot = -1;
             } else {
@@ -335,8 +352,51 @@ struct Server {
             ih.push_back(r->host_inst);
         }
         const std::vector<int> order = order_jobs(jobs);
-        int rc0 = assign_groups(jobs, order);
+        // Estimated work, from rates measured on gfx950 (300 to 2000 missions): a
+        // one-workgroup solve evaluates about 2.5e9 move slots/s, a workgroup of the
+        // HBM-resident schedule about 1.9e9, plus about 15 us per iteration for its
+        // exchange, apply and record rebuild.
+        constexpr double kWgRate = 2.5e9, kGlRate = 1.9e9, kGlIter = 15e-6;
+        double w_wg = 0, w_gl = 0, wg_long = 0;
+        uint32_t lds = 0;
+        bool same = true;
+        for (const JobHost &h : jobs) {
+            if (h.kind == AT_SCHED_GLOBAL) {
+                w_gl += (double)h.iters * ((double)h.slots / kGlRate + kGlIter);
+            } else {
+                w_wg += (double)h.iters * (double)h.slots / kWgRate;
+                wg_long = std::max(wg_long, (double)h.iters * (double)h.slots / kWgRate);
+            }
+            lds = std::max(lds, h.lds);
+            same = same && h.esz16 == jobs[0].esz16 && h.tb16 == jobs[0].tb16;
+        }
+        // Both kinds resident: one grid runs them (launch_jobs), its workers for the
+        // one-workgroup solves in proportion to their share of the work, so both
+        // kinds end about together
+        int workers = 0, gmax = 0;
+        if (w_wg > 0 && w_gl > 0 && same) {
+            const int cap = max_groups_mixed(lds, jobs[0].tb16, jobs[0].esz16);
+            if (cap >= 2) {
+                workers = std::max(1, std::min((int)std::ceil(cap * w_wg / (w_wg + w_gl)), cap / 2));
+                gmax = cap - workers;
+            }
+        }
+        int rc0 = assign_groups(jobs, order, gmax);
         if (rc0) return rc0;
+        // HBM-resident solves that would finish before the launch's longest part
+        // run more iterations (up to all that remain), on the same estimate: their
+        // workgroups stay busy, and they leave the server sooner
+        double span = workers > 0 ? std::max(wg_long, w_wg / workers) : 0.0;
+        for (const JobHost &h : jobs)
+            if (h.kind == AT_SCHED_GLOBAL)
+                span = std::max(span, (double)h.iters * ((double)h.slots / ((double)h.groups * kGlRate) + kGlIter));
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            JobHost &h = jobs[k];
+            if (h.kind != AT_SCHED_GLOBAL) continue;
+            const double per = (double)h.slots / ((double)h.groups * kGlRate) + kGlIter;
+            const int64_t more = (int64_t)(span / per);
+            h.iters = std::min<int64_t>(active[k]->pr.max_iters - active[k]->t, std::max<int64_t>(h.iters, more));
+        }
         std::vector<JobDev> hj(jobs.size());
         for (size_t k = 0; k < order.size(); ++k) {
             Request *r = active[(size_t)order[k]];
@@ -350,12 +410,13 @@ struct Server {
         }
         // the host copy of the table stays alive until the launch has completed
         table.swap(hj);
-        hipError_t e = hipMemcpyAsync(djobs, table.data(), sizeof(JobDev) * table.size(),
-                                      hipMemcpyHostToDevice, s);
+        hipError_t e = hipStreamWaitEvent(ls, adm_ev, 0);   // the admitted records are in place
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(djobs, table.data(), sizeof(JobDev) * table.size(), hipMemcpyHostToDevice, ls);
         if (e != hipSuccess) return hip_fail(e, "server: job upload");
-        int rc = launch_jobs(jobs, order, djobs, xs, s);
+        int rc = launch_jobs(jobs, order, djobs, xs, ls, workers);
         if (rc) return rc;
-        if ((e = hipEventRecord(done_ev, s)) != hipSuccess) return hip_fail(e, "server: event");
+        if ((e = hipEventRecord(done_ev, ls)) != hipSuccess) return hip_fail(e, "server: event");
         in_flight = true;
         return AT_OK;
     }
@@ -406,6 +467,17 @@ int at_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t chunk_i
     if ((e = hipEventCreateWithFlags(&sv->done_ev, hipEventDisableTiming)) != hipSuccess) {
         delete sv;
         return hip_fail(e, "server event");
+    }
+    if ((e = hipEventCreateWithFlags(&sv->adm_ev, hipEventDisableTiming)) != hipSuccess) {
+        sv->adm_ev = nullptr;
+        delete sv;
+        return hip_fail(e, "server event");
+    }
+    // default priority, and no implicit ordering with the caller's (possibly null) stream
+    if ((e = hipStreamCreateWithFlags(&sv->ls, hipStreamNonBlocking)) != hipSuccess) {
+        sv->ls = nullptr;
+        delete sv;
+        return hip_fail(e, "server launch stream");
     }
     *server = sv;
     return AT_OK;
@@ -502,6 +574,21 @@ int at_server_poll(void *server, uint64_t ticket, at_result *out)
     delete r;
     if (e != hipSuccess) return hip_fail(e, "server: result copy");
     return status == AT_OK ? AT_OK : fail(status, "request failed with status %d", status);
+}
+
+int at_server_completed(void *server, uint64_t *tickets, int32_t capacity, int32_t *n_out)
+{
+    Server *sv = (Server *)server;
+    if (!sv || !n_out || (capacity > 0 && !tickets)) return fail(AT_EINVAL, "null argument");
+    if (capacity < 0) return fail(AT_EINVAL, "negative capacity");
+    int32_t n = 0;
+    while (n < capacity && !sv->finished.empty()) {
+        const uint64_t t = sv->finished.front();
+        sv->finished.pop_front();
+        if (sv->all.count(t)) tickets[n++] = t;   // skip tickets already polled
+    }
+    *n_out = n;
+    return AT_OK;
 }
 
 int at_server_destroy(void *server)

@@ -163,3 +163,35 @@ def test_admission_batch_over_one_scatter_round():
     for k in (0, 299):
         _, o = oracle_solve(insts[k], tenure=3, iters=20)
         assert_same_result(o, got[tickets[k]], f"request {k} of 300 vs oracle")
+
+
+def test_completed_lists_each_finished_ticket_once():
+    """at_server_completed: every request appears once, only after it is done,
+    and its poll then succeeds; a ticket polled before it is listed is not
+    listed afterwards."""
+    reqs = _requests()
+    devs = [_dev(i) for i, _ in reqs]
+    alone = [at.solve(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    srv = at.Server(1 << 30, max_slots=3, chunk_iters=40)
+    tickets = [srv.submit(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    early = tickets[0]
+    seen, got = [], {}
+    for _ in range(200000):
+        srv.progress()
+        if early not in got:
+            r = srv.poll(early)          # polled directly, without the list
+            if r is not None:
+                got[early] = r
+        for t in srv.completed(capacity=2):
+            assert t not in seen and t != early
+            seen.append(t)
+            r = srv.poll(t)
+            assert r is not None
+            got[t] = r
+        if len(got) == len(tickets):
+            break
+    assert sorted(seen) == sorted(tickets[1:])
+    assert srv.completed() == []
+    for k, t in enumerate(tickets):
+        _same(alone[k], got[t], f"request {k}")
+    srv.close()
