@@ -100,8 +100,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-plain", type=int, default=400,
                     help="requests of the stream also solved one at_solve at a time (the plain form)")
-    ap.add_argument("--serve-chunk", type=int, default=500, help="iterations per serving launch")
-    ap.add_argument("--serve-slots", type=int, default=256, help="concurrent solves in the server")
+    ap.add_argument("--serve-chunk", type=int, default=250,
+                    help="iterations per serving launch, at least, of a solve that runs on its own workgroups")
+    ap.add_argument("--serve-slots", type=int, default=1024, help="concurrent solves in the server")
     ap.add_argument("--stress", type=int, default=1000,
                     help="also run the 256 x 10000 stress instance for this many iterations "
                          "(Tabu and NS; 0: skip)")

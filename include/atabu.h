@@ -258,11 +258,16 @@ int at_debug_eval_moves(const at_instance *inst, const at_params *params,
 /* Serving with continuous batching.  A server owns device memory up to
  * hbm_budget_bytes and up to max_slots concurrent solves.  Submitted requests
  * wait until a slot and enough budget are free, then join the solves already
- * on the GPU: the device advances every resident solve at least `chunk_iters`
- * iterations per launch (a one-workgroup solve with S move slots per
- * iteration, S < 2^20, runs floor(2^20 / S) times as many, up to the rest of
- * its budget), so requests that arrive while others run start within one
- * chunk.  Each request's result is the same as at_solve's.
+ * on the GPU: every launch advances each resident solve at least `chunk_iters`
+ * iterations or all that remain.  Solves short enough to finish within the
+ * launch on one workgroup run to the end, taken from a queue by the launch's
+ * worker workgroups; longer ones get workgroups of their own for at least
+ * chunk_iters iterations, so requests that arrive while others run start
+ * within one launch.  (When the resident solves differ in entry or tabu width,
+ * each launch instead runs chunk_iters iterations of every solve, and a
+ * one-workgroup solve with S move slots per iteration, S < 2^20,
+ * floor(2^20 / S) times as many.)  Each request's result is the same as
+ * at_solve's.
  * `stream` is the caller's: requests are admitted (their instance arrays read)
  * and results copied out on it; the solves themselves run on an internal
  * stream of default priority, so a poll never waits for the launch in flight.

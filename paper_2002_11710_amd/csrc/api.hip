@@ -295,7 +295,7 @@ static int pick_chunk(const at_params &pr, int64_t slots)
 
 // Missions per block of a global-schedule job for its group count: one block
 // per workgroup where LDS allows, else the LDS limit.
-static void set_block_size(JobHost &h)
+void set_block_size(JobHost &h)
 {
     // as few rounds of blocks as LDS allows, then the smallest blocks with that many rounds
     const int64_t g = std::max(1, h.groups);
@@ -436,6 +436,7 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.gk = h.gk;
     j.g0 = h.g0;
     j.ng = h.groups;
+    j.sched = h.kind;
     return AT_OK;
 }
 
@@ -491,10 +492,8 @@ int release_class_streams()
 // streams.  Then, in order on the caller's stream: one cooperative launch per
 // group of HBM-resident jobs that assign_groups put together (each job on its
 // own range of the grid), and one cooperative launch per multi-workgroup job.
-// With wg_workers > 0 the two first kinds can instead share one grid (see
-// engine.h).
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
-                Xchg *xs, hipStream_t s, int wg_workers)
+                Xchg *xs, hipStream_t s)
 {
     hipError_t e;
     const int n = (int)order.size();
@@ -538,30 +537,6 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
         }
         return AT_OK;
     };
-    // Both kinds present, the one-workgroup jobs of the global jobs' entry and tabu
-    // widths and the global jobs in one launch: one grid runs them all, wg_workers
-    // workgroups taking the one-workgroup jobs from the queue (k_search_mixed).
-    if (wg_workers > 0 && !cls.empty() && k < n) {
-        const JobHost &g0 = jobs[(size_t)order[(size_t)k]];
-        bool fuse = true;
-        uint32_t lds = 0;
-        int n_ggroups = 0;
-        for (int q = 0; q < n && fuse; ++q) {
-            const JobHost &h = jobs[(size_t)order[(size_t)q]];
-            const bool global = q >= k;
-            if (h.esz16 != g0.esz16 || h.tb16 != g0.tb16) fuse = false;
-            if (global && (h.kind != AT_SCHED_GLOBAL || h.launch != g0.launch || h.block != kGlobalBlock)) fuse = false;
-            if (!global && (h.kind != AT_SCHED_WG || h.wtile)) fuse = false;
-            lds = std::max(lds, h.lds);
-            if (global) n_ggroups = std::max(n_ggroups, h.g0 + h.groups);
-        }
-        if (fuse) {
-            if ((e = fill_u32(xs->queues, 0u, 1, s)) != hipSuccess) return hip_fail(e, "reset queue");
-            e = launch_search_mixed(dj + k, n - k, n_ggroups, dj, k, &xs->queues[0], wg_workers, lds, g0.tb16,
-                                    g0.esz16, s);
-            return e == hipSuccess ? AT_OK : hip_fail(e, "search launch (both schedules)");
-        }
-    }
     if (!cls.empty()) {
         if ((e = fill_u32(xs->queues, 0u, kMaxClasses, s)) != hipSuccess) return hip_fail(e, "reset queues");
         hipEvent_t fork = nullptr;
@@ -660,7 +635,7 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
 // into cooperative launches and give each job a range of its launch's
 // workgroups: as many as it asked for when they all fit the co-resident
 // limit, else shares proportional to the request (at least one each).
-int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order, int max_groups)
+int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order)
 {
     const int n = (int)order.size();
     int k = 0, launch = 0;
@@ -675,8 +650,7 @@ int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order, int
             lds = std::max(lds, h.lds);
             ++e;
         }
-        int cap = max_groups_global(hf.block, lds, hf.tb16, hf.esz16);
-        if (max_groups > 0) cap = std::min(cap, max_groups);
+        const int cap = max_groups_global(hf.block, lds, hf.tb16, hf.esz16);
         if (cap < 1) return fail(AT_EDEVICE, "cannot co-schedule the HBM-resident search");
         for (int a = k; a < e; a += cap, ++launch) {
             const int b = std::min(e, a + cap);

@@ -140,6 +140,7 @@ struct JobDev {
     int32_t form;                     // AT_FORM_BEST or AT_FORM_SWEEP (wave schedule)
     int32_t gk;                       // global schedule: missions staged per block
     int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
+    int32_t sched;                    // AT_SCHED_* the solve runs on
     uint64_t seed;
     int32_t *out_off, *out_seq, *out_of;
     int32_t *fin_off, *fin_seq;       // routes after the last iteration (may be null)
@@ -244,8 +245,11 @@ hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int bl
 hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 int max_groups_global(int block, uint32_t lds_bytes, int tb16, int esz16);
-// One grid for both kinds (block kGlobalBlock): n_ggroups workgroups for the
-// global jobs, n_workers taking one-workgroup jobs from queue[0]; cooperative.
+// One grid for both kinds (block kGlobalBlock), cooperative: n_ggroups
+// workgroups for the global jobs `gjobs` (each on its range), n_workers taking
+// the jobs of `wjobs` from queue[0]: one-workgroup jobs, and global jobs run on
+// a single workgroup (sched says which).  Resets every global job's exchange
+// state first.
 hipError_t launch_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups, const JobDev *wjobs, int n_wjobs,
                                uint32_t *queue, int n_workers, uint32_t lds_bytes, int tb16, int esz16,
                                hipStream_t s);

@@ -54,14 +54,10 @@ int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, 
 int plan_job(JobHost &h, const InstDev &d, bool alone);
 int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal);
 int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s);
-// wg_workers > 0: when one-workgroup jobs and a single launch of HBM-resident
-// jobs (of the same entry and tabu widths) are both present, they run in one
-// grid, wg_workers workgroups taking the one-workgroup jobs from a queue beside
-// the global jobs' workgroups (assign_groups was limited to leave room for them).
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,
-                Xchg *xs, hipStream_t s, int wg_workers = 0);
+                Xchg *xs, hipStream_t s);
 std::vector<int> order_jobs(const std::vector<JobHost> &jobs);
-// max_groups > 0: at most that many workgroups per launch for the HBM-resident jobs
-int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order, int max_groups = 0);
+int assign_groups(std::vector<JobHost> &jobs, const std::vector<int> &order);
+void set_block_size(JobHost &h);
 
 }  // namespace at

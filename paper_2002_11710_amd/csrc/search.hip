@@ -1856,12 +1856,14 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_global(const JobDev *jo
 }
 
 // One-workgroup jobs and HBM-resident jobs of one launch in one grid:
-// workgroups [0, n_ggroups) run the global jobs as k_search_global does, the
-// others take one-workgroup jobs from the queue as k_search_wg does (with this
-// kernel's block size).  The two kinds share the device inside one
-// cooperative launch, so every workgroup is resident and nothing waits for
-// another stream.  A worker passes the job index through the first word of
-// its LDS between two barriers, before the job's own use of it.
+// workgroups [0, n_ggroups) run the global jobs of `gjobs` as k_search_global
+// does, the others (workers) take jobs of `wjobs` from the queue: one-workgroup
+// jobs as k_search_wg does (with this kernel's block size), and global jobs on
+// one workgroup.  The two kinds share the device inside one cooperative launch,
+// so every workgroup is resident and nothing waits for another stream, and a
+// worker that finishes a solve takes the next instead of idling until the
+// launch ends.  A worker passes the job index through the first word of its
+// LDS between two barriers, before the job's own use of it.
 template <typename TE, typename TB>
 __global__ void __launch_bounds__(kGlobalBlock) k_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups,
                                                               const JobDev *wjobs, int n_wjobs, uint32_t *queue)
@@ -1879,7 +1881,14 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_mixed(const JobDev *gjo
         const int j = *s_job;
         __syncthreads();
         if (j >= n_wjobs) return;
-        run_job<TE, TB, false>(wjobs[j], smem, 0, 1, nullptr);
+        const JobDev &J = wjobs[j];
+        if (J.sched == AT_SCHED_GLOBAL) {
+            const InstDev &I = *J.inst;
+            const uint32_t lds = global_lds_bytes(J.gk, I.R, I.C, I.M, I.V, (int)sizeof(TE), (int)sizeof(TB));
+            run_job_global<TE, TB>(J, 0, 1, smem, (uint64_t *)(smem + lds - 2048));
+        } else {
+            run_job<TE, TB, false>(J, smem, 0, 1, nullptr);
+        }
         __syncthreads();
     }
 }
@@ -1889,6 +1898,7 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_mixed(const JobDev *gjo
 // carries, and the abort flag is cleared.
 __global__ void k_reset_global(const JobDev *jobs, int n_jobs)
 {
+    if (jobs[blockIdx.x].sched != AT_SCHED_GLOBAL) return;   // a one-workgroup job of a mixed launch
     GlobalBufs &B = *jobs[blockIdx.x].gb;
     for (int w = (int)threadIdx.x; w < 2 * kMaxGroups; w += (int)blockDim.x) B.slots[w * kSlotStride] = ~0ull;
     if (threadIdx.x == 0) B.abort = 0;
@@ -2095,7 +2105,10 @@ hipError_t launch_search_mixed(const JobDev *gjobs, int n_gjobs, int n_ggroups, 
                                uint32_t *queue, int n_workers, uint32_t lds_bytes, int tb16, int esz16,
                                hipStream_t s)
 {
-    k_reset_global<<<dim3((unsigned)n_gjobs), dim3(256), 0, s>>>(gjobs, n_gjobs);
+    // the two lists are consecutive in the table (workers' jobs first)
+    const JobDev *all = n_wjobs > 0 ? wjobs : gjobs;
+    if (n_wjobs > 0 && n_gjobs > 0 && gjobs != wjobs + n_wjobs) return hipErrorInvalidValue;
+    if (n_wjobs + n_gjobs > 0) k_reset_global<<<dim3((unsigned)(n_wjobs + n_gjobs)), dim3(256), 0, s>>>(all, n_wjobs + n_gjobs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define AT_MX(TE, TB) \

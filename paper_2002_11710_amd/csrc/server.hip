@@ -5,12 +5,12 @@
 // admitted: its instance is prepared into the arena (checks + compact travel
 // block), and it joins the resident solves.  Every at_server_progress call
 // that finds the device idle retires finished solves, admits waiting
-// requests, and launches the next chunk: every resident solve advances
-// `chunk_iters` iterations from its saved state (routes, tabu table,
-// iteration, objectives), so a request that arrives while others run starts
-// at the next chunk boundary and shares the GPU with them.  Because every
-// solve is deterministic and resumes exactly where it stopped, its result does
-// not depend on what else is resident or on the chunking.
+// requests, and launches the next chunk: every resident solve advances at
+// least `chunk_iters` iterations (or to its end) from its saved state
+// (routes, tabu table, iteration, objectives), so a request that arrives while
+// others run starts at the next launch and shares the GPU with them.  Because
+// every solve is deterministic and resumes exactly where it stopped, its
+// result does not depend on what else is resident or on the chunking.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -332,72 +332,40 @@ struct Server {
         return AT_OK;
     }
 
+    // Estimated times, from rates measured on gfx950 (300 to 2000 missions): a
+    // one-workgroup solve evaluates about 2.5e9 move slots/s, a workgroup of the
+    // HBM-resident schedule about 1.9e9, plus about 15 us per iteration for its
+    // exchange, apply and record rebuild.
+    static constexpr double kWgRate = 2.5e9, kGlRate = 1.9e9, kGlIter = 15e-6;
+
+    // Launch the next chunk of every active solve.
     int launch()
     {
         if (active.empty()) return AT_OK;
-        std::vector<JobHost> jobs;
-        std::vector<InstDev> ih;
-        jobs.reserve(active.size());
-        for (size_t k = 0; k < active.size(); ++k) {
-            const Request *r = active[k];
-            JobHost h = r->job;
-            h.inst = (int)k;
-            // a one-workgroup solve with few move slots runs proportionally more
-            // iterations per chunk (up to all that remain): small requests finish
-            // in the chunk they were admitted in instead of waiting out the large ones
-            int64_t it = chunk;
-            if (h.kind == AT_SCHED_WG) it *= std::max<int64_t>(1, kChunkSlots / std::max<int64_t>(1, h.slots));
-            h.iters = std::min<int64_t>(r->pr.max_iters - r->t, it);
-            jobs.push_back(h);
-            ih.push_back(r->host_inst);
-        }
-        const std::vector<int> order = order_jobs(jobs);
-        // Estimated work, from rates measured on gfx950 (300 to 2000 missions): a
-        // one-workgroup solve evaluates about 2.5e9 move slots/s, a workgroup of the
-        // HBM-resident schedule about 1.9e9, plus about 15 us per iteration for its
-        // exchange, apply and record rebuild.
-        constexpr double kWgRate = 2.5e9, kGlRate = 1.9e9, kGlIter = 15e-6;
-        double w_wg = 0, w_gl = 0, wg_long = 0;
-        uint32_t lds = 0;
+        const size_t n = active.size();
+        std::vector<JobHost> jobs(n);
         bool same = true;
-        for (const JobHost &h : jobs) {
-            if (h.kind == AT_SCHED_GLOBAL) {
-                w_gl += (double)h.iters * ((double)h.slots / kGlRate + kGlIter);
-            } else {
-                w_wg += (double)h.iters * (double)h.slots / kWgRate;
-                wg_long = std::max(wg_long, (double)h.iters * (double)h.slots / kWgRate);
-            }
-            lds = std::max(lds, h.lds);
-            same = same && h.esz16 == jobs[0].esz16 && h.tb16 == jobs[0].tb16;
+        uint32_t lds = 0;
+        for (size_t k = 0; k < n; ++k) {
+            jobs[k] = active[k]->job;
+            jobs[k].inst = (int)k;
+            same = same && jobs[k].esz16 == jobs[0].esz16 && jobs[k].tb16 == jobs[0].tb16;
+            lds = std::max(lds, jobs[k].lds);
         }
-        // Both kinds resident: one grid runs them (launch_jobs), its workers for the
-        // one-workgroup solves in proportion to their share of the work, so both
-        // kinds end about together
-        int workers = 0, gmax = 0;
-        if (w_wg > 0 && w_gl > 0 && same) {
-            const int cap = max_groups_mixed(lds, jobs[0].tb16, jobs[0].esz16);
-            if (cap >= 2) {
-                workers = std::max(1, std::min((int)std::ceil(cap * w_wg / (w_wg + w_gl)), cap / 2));
-                gmax = cap - workers;
-            }
-        }
-        int rc0 = assign_groups(jobs, order, gmax);
-        if (rc0) return rc0;
-        // HBM-resident solves that would finish before the launch's longest part
-        // run more iterations (up to all that remain), on the same estimate: their
-        // workgroups stay busy, and they leave the server sooner
-        double span = workers > 0 ? std::max(wg_long, w_wg / workers) : 0.0;
-        for (const JobHost &h : jobs)
-            if (h.kind == AT_SCHED_GLOBAL)
-                span = std::max(span, (double)h.iters * ((double)h.slots / ((double)h.groups * kGlRate) + kGlIter));
-        for (size_t k = 0; k < jobs.size(); ++k) {
-            JobHost &h = jobs[k];
-            if (h.kind != AT_SCHED_GLOBAL) continue;
-            const double per = (double)h.slots / ((double)h.groups * kGlRate) + kGlIter;
-            const int64_t more = (int64_t)(span / per);
-            h.iters = std::min<int64_t>(active[k]->pr.max_iters - active[k]->t, std::max<int64_t>(h.iters, more));
-        }
-        std::vector<JobDev> hj(jobs.size());
+        const int cap = same ? max_groups_mixed(lds, jobs[0].tb16, jobs[0].esz16) : 0;
+        int rc = cap >= 1 ? plan_pooled(jobs, cap) : plan_classes(jobs);
+        if (rc) return rc;
+        hipError_t e;
+        if ((e = hipEventRecord(done_ev, ls)) != hipSuccess) return hip_fail(e, "server: event");
+        in_flight = true;
+        return AT_OK;
+    }
+
+    // Fill the job table in `order` (iterations from jobs[].iters) and upload it
+    // on the launch stream once the admitted records are in place.
+    int upload_table(const std::vector<JobHost> &jobs, const std::vector<int> &order)
+    {
+        std::vector<JobDev> hj(order.size());
         for (size_t k = 0; k < order.size(); ++k) {
             Request *r = active[(size_t)order[k]];
             int rc = fill_job(hj[k], jobs[(size_t)order[k]], r->dinst, r->scal);
@@ -410,15 +378,125 @@ struct Server {
         }
         // the host copy of the table stays alive until the launch has completed
         table.swap(hj);
-        hipError_t e = hipStreamWaitEvent(ls, adm_ev, 0);   // the admitted records are in place
+        hipError_t e = hipStreamWaitEvent(ls, adm_ev, 0);
         if (e == hipSuccess)
             e = hipMemcpyAsync(djobs, table.data(), sizeof(JobDev) * table.size(), hipMemcpyHostToDevice, ls);
-        if (e != hipSuccess) return hip_fail(e, "server: job upload");
-        int rc = launch_jobs(jobs, order, djobs, xs, ls, workers);
+        return e == hipSuccess ? AT_OK : hip_fail(e, "server: job upload");
+    }
+
+    // One grid for every solve (all of one entry and tabu width; `cap` workgroups
+    // fit the device).  For a launch length T: a solve whose remaining iterations
+    // fit T on one workgroup goes to the workers' queue with all of them; a longer
+    // (HBM-resident) one gets a range of workgroups, as few as let chunk_iters
+    // iterations fit T (at most one per 16384 move slots); the workers are as
+    // many as the queue's total time over T.  T is the shortest length whose plan
+    // fits the grid.  A solve with its own range that would finish before the
+    // launch's longest part runs more iterations, up to all that remain.  A worker
+    // that finishes a solve takes the next (longest first), so no workgroup waits
+    // out the launch while solves are queued.
+    int plan_pooled(std::vector<JobHost> &jobs, int cap)
+    {
+        const size_t n = jobs.size();
+        std::vector<int64_t> rem(n);
+        std::vector<double> full(n);   // all remaining iterations on one workgroup
+        for (size_t k = 0; k < n; ++k) {
+            const JobHost &h = jobs[k];
+            rem[k] = active[k]->pr.max_iters - active[k]->t;
+            full[k] = h.kind == AT_SCHED_GLOBAL ? (double)rem[k] * ((double)h.slots / kGlRate + kGlIter)
+                                                : (double)rem[k] * (double)h.slots / kWgRate;
+        }
+        std::vector<int> g(n, 0);
+        auto per_iter = [&](size_t k, int groups) {
+            return (double)jobs[k].slots / ((double)groups * kGlRate) + kGlIter;
+        };
+        auto plan = [&](double T, bool keep) {
+            int64_t need = 0;
+            double pooled = 0;
+            for (size_t k = 0; k < n; ++k) {
+                int gk = 0;
+                if (jobs[k].kind == AT_SCHED_GLOBAL && full[k] > T) {
+                    const double it = (double)std::min<int64_t>(rem[k], chunk);
+                    const double per = T / it - kGlIter;
+                    const int64_t ask = std::max<int64_t>(1, jobs[k].slots / 16384);
+                    const int64_t x = per <= 0 ? ask : (int64_t)std::ceil((double)jobs[k].slots / (kGlRate * per));
+                    gk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(x, ask), cap));
+                    need += gk;
+                } else {
+                    pooled += full[k];
+                }
+                if (keep) g[k] = gk;
+            }
+            if (pooled > 0) need += std::max<int64_t>(1, (int64_t)std::ceil(pooled / T));
+            return need;
+        };
+        double lo = 1e-5, hi = 1e4;   // seconds
+        for (int i = 0; i < 64; ++i) {
+            const double mid = std::sqrt(lo * hi);
+            if (plan(mid, false) <= cap) hi = mid; else lo = mid;
+        }
+        if (plan(hi, true) > cap) return fail(AT_EDEVICE, "server: the resident solves do not fit one launch");
+        double span = hi;
+        int ranged = 0;
+        std::vector<int> pool, own;
+        for (size_t k = 0; k < n; ++k) {
+            if (g[k] > 0) {
+                ranged += g[k];
+                own.push_back((int)k);
+                span = std::max(span, (double)std::min<int64_t>(rem[k], chunk) * per_iter(k, g[k]));
+            } else {
+                pool.push_back((int)k);
+                span = std::max(span, full[k]);
+            }
+        }
+        for (size_t k = 0; k < n; ++k) {
+            JobHost &h = jobs[k];
+            if (g[k] > 0) {
+                const int64_t more = (int64_t)(span / per_iter(k, g[k]));
+                h.groups = g[k];
+                h.iters = std::min<int64_t>(rem[k], std::max<int64_t>(std::min<int64_t>(rem[k], chunk), more));
+            } else {
+                h.groups = 1;
+                h.iters = rem[k];
+            }
+            if (h.kind == AT_SCHED_GLOBAL) set_block_size(h);
+        }
+        std::stable_sort(pool.begin(), pool.end(), [&](int a, int b) { return full[(size_t)a] > full[(size_t)b]; });
+        int g0 = 0;
+        for (int k : own) {
+            jobs[(size_t)k].g0 = g0;
+            g0 += jobs[(size_t)k].groups;
+        }
+        std::vector<int> order = pool;
+        order.insert(order.end(), own.begin(), own.end());
+        uint32_t lds = 0;
+        for (const JobHost &h : jobs) lds = std::max(lds, h.lds);
+        int rc = upload_table(jobs, order);
         if (rc) return rc;
-        if ((e = hipEventRecord(done_ev, ls)) != hipSuccess) return hip_fail(e, "server: event");
-        in_flight = true;
-        return AT_OK;
+        const int workers = pool.empty() ? 0 : cap - ranged;
+        hipError_t e = fill_u32(xs->queues, 0u, 1, ls);
+        if (e == hipSuccess)
+            e = launch_search_mixed(djobs + pool.size(), (int)own.size(), ranged, djobs, (int)pool.size(),
+                                    &xs->queues[0], workers, lds, jobs[0].tb16, jobs[0].esz16, ls);
+        return e == hipSuccess ? AT_OK : hip_fail(e, "server: search launch");
+    }
+
+    // Solves of several entry or tabu widths: one launch per class of
+    // one-workgroup solves (concurrently), then the HBM-resident ones.  Each
+    // advances chunk_iters iterations; a one-workgroup solve with S move slots,
+    // S < 2^20, floor(2^20 / S) times as many, up to all that remain.
+    int plan_classes(std::vector<JobHost> &jobs)
+    {
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            JobHost &h = jobs[k];
+            int64_t it = chunk;
+            if (h.kind == AT_SCHED_WG) it *= std::max<int64_t>(1, kChunkSlots / std::max<int64_t>(1, h.slots));
+            h.iters = std::min<int64_t>(active[k]->pr.max_iters - active[k]->t, it);
+        }
+        const std::vector<int> order = order_jobs(jobs);
+        int rc = assign_groups(jobs, order);
+        if (!rc) rc = upload_table(jobs, order);
+        if (!rc) rc = launch_jobs(jobs, order, djobs, xs, ls);
+        return rc;
     }
 };
 

@@ -195,3 +195,21 @@ def test_completed_lists_each_finished_ticket_once():
     for k, t in enumerate(tickets):
         _same(alone[k], got[t], f"request {k}")
     srv.close()
+
+
+def test_mixed_tabu_widths_resume_in_chunks():
+    """Resident solves of two tabu-entry widths (one budget above 2^16
+    iterations) cannot share one grid: each launch then runs chunk_iters
+    iterations of every solve, which resume from their saved state; every
+    result equals the request alone."""
+    reqs = _requests()[:4]
+    reqs.append((make_instance(377, 20, 2, 2, 12), dict(variant=at.AT_TABU, tenure=6, iters=70000,
+                                                         restart_seed=5, trace=True)))
+    devs = [_dev(i) for i, _ in reqs]
+    alone = [at.solve(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    srv = at.Server(1 << 30, max_slots=8, chunk_iters=9)
+    tickets = [srv.submit(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    got = _drive(srv, list(tickets))
+    for k, t in enumerate(tickets):
+        _same(alone[k], got[t], f"request {k}")
+    srv.close()
