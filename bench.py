@@ -37,6 +37,9 @@ OPS_RELOCATE, OPS_SWAP = 6, 10
 # gather counted as one 4-byte bank access: relocate = 2 travel gathers, swap = 4 travel
 # gathers + the partner's tabu entry (records are wavefront broadcasts, not counted)
 LDS_RELOCATE, LDS_SWAP = 8, 20
+# travel-time reads a move's delta needs beyond the per-position records (2-byte
+# gathers at data-dependent addresses): relocate 2, swap 4
+GATHERS_RELOCATE, GATHERS_SWAP = 2, 4
 # LDS bandwidth: 128 bytes per clock per CU x 256 CUs x 2.4 GHz
 LDS_PEAK_BPS = 128 * 256 * 2.4e9
 COUNTERS = os.path.join(ROOT, "profiles", "counters.txt")
@@ -149,6 +152,19 @@ def lds_peak(strides=(1, 2, 4, 8, 16, 32, 64, 128)):
            "B_per_clk_per_CU": (nbytes / (ms / 1000.0)) / (cus * ghz * 1e9) if ghz else None}
     base = run(2000, 1)[0]
     out["stride_slowdown"] = {str(s): run(2000, s)[0] / base for s in strides}
+    # random 2-byte gathers (the travel reads of the move deltas)
+    L.ldspeak_gather_run.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                     C.POINTER(C.c_uint64)]
+    ms2, clk2, wt2 = C.c_double(0), C.c_uint64(0), C.c_uint64(0)
+    giters = 20000
+    rc = L.ldspeak_gather_run(blocks, giters, C.byref(ms2), C.byref(clk2), C.byref(wt2))
+    if rc != 0:
+        raise RuntimeError(f"ldspeak_gather_run: HIP error {rc}")
+    gathers = blocks * 1024 * giters * 8
+    out["random_u16_gathers_per_s"] = gathers / (ms2.value / 1000.0)
+    out["random_u16_GBps"] = 2 * gathers / (ms2.value / 1000.0) / 1e9
+    if ghz:
+        out["random_u16_wave_reads_per_clk_per_CU"] = gathers / 64 / (ms2.value / 1000.0) / (cus * ghz * 1e9)
     return out
 
 
@@ -395,6 +411,13 @@ def main():
                                         peak_source="measured (ldspeak)",
                                         nominal_peak_GBps=LDS_PEAK_BPS / 1e9,
                                         frac_of_nominal=line["batch"]["lds_bytes_per_s"] / LDS_PEAK_BPS)
+            # the bound of the access pattern: the travel reads are 2-byte gathers at
+            # data-dependent addresses, whose bank conflicts cap them far below the
+            # conflict-free peak; the probe measures that cap
+            gp = line["lds_peak"]["random_u16_gathers_per_s"]
+            line["lds_roofline"].update(travel_gathers_per_s=line["batch"]["travel_gathers_per_s"],
+                                        random_gather_peak_per_s=gp,
+                                        gather_frac=line["batch"]["travel_gathers_per_s"] / gp)
     if args.fleet:
         line["fleet"] = bench_fleet(args.fleet, plain=not args.no_plain)
     if args.stress:
@@ -440,18 +463,21 @@ def bench_batch(n_inst: int, restarts: int = 8, plain: bool = True):
     evals = 0
     ops = 0
     lds = 0
+    gathers = 0
     for s in specs:
         rel, swp = move_counts(s["n_missions"], s["n_vehicles"])
         evals += restarts * 2000 * (rel + swp)
         ops += restarts * 2000 * (rel * OPS_RELOCATE + swp * OPS_SWAP)
         lds += restarts * 2000 * (rel * LDS_RELOCATE + swp * LDS_SWAP)
+        gathers += restarts * 2000 * (rel * GATHERS_RELOCATE + swp * GATHERS_SWAP)
     kms = float(res.search_ms[0])
     assert (res.status == 0).all()
     out = {"instances": n_inst, "restarts": restarts, "solves": n_inst * restarts,
            "wall_s": wall, "solves_per_s": n_inst * restarts / wall,
            "move_evals_per_s": evals / wall, "search_ms": kms,
            "alu_frac": ops / (kms / 1000.0) / ALU_PEAK_OPS,
-           "lds_bytes_per_s": lds / (kms / 1000.0)}
+           "lds_bytes_per_s": lds / (kms / 1000.0),
+           "travel_gathers_per_s": gathers / (kms / 1000.0)}
     if not plain:
         return out
     # the plain per-instance form: one at_solve launch per (instance, restart), in
