@@ -298,12 +298,23 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
     const int remb = pb.y - pb.x + kPackBias;
     const int Gi = ii + ri;
     const uint32_t ibase = (uint32_t)m * (uint32_t)c.NG;
+    // the unit's gap records (at most 64 columns), one per lane, read once and
+    // handed to the column loop with readlane: one coalesced LDS read per unit
+    // instead of a 16-byte broadcast per column
+    const int gl_i = G0 + (lane < G1 - G0 ? lane : 0);
+    const int4 gl = c.gap[gl_i];
+    const int gel = c.gend[gl_i];
+    auto col = [&](int G) {
+        const int k = G - G0;
+        return make_int4(__builtin_amdgcn_readlane(gl.x, k), __builtin_amdgcn_readlane(gl.y, k),
+                         __builtin_amdgcn_readlane(gl.z, k), 0);
+    };
     uint64_t best = kKeyNone;
     int G = G0;
     while (G < G1) {
-        // the segment's vehicle and end: two independent loads
-        const int r = c.gap[G].w & 0xFFFF;
-        const int Gend = min(G1, (int)c.gend[G]);
+        // the segment's vehicle and end
+        const int r = __builtin_amdgcn_readlane(gl.w, G - G0) & 0xFFFF;
+        const int Gend = min(G1, __builtin_amdgcn_readlane(gel, G - G0));
         const bool tb = use_tabu && (int)tabu[r * c.M + m] > t;
         uint32_t pm = 0xFFFFFFFFu;
         // four columns per step: all their LDS reads are in flight together
@@ -312,19 +323,19 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
         if (r < rlo || r > rhi) {
             // no lane of this tile flies vehicle r: no gap is a lane's own
             for (; G + 4 <= Gend; G += 4) {
-                const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+                const int4 g0 = col(G), g1 = col(G + 1), g2 = col(G + 2), g3 = col(G + 3);
                 pm = AT_RELOC(g0, G);
                 pm = AT_RELOC(g1, G + 1);
                 pm = AT_RELOC(g2, G + 2);
                 pm = AT_RELOC(g3, G + 3);
             }
             for (; G < Gend; ++G) {
-                const int4 g0 = c.gap[G];
+                const int4 g0 = col(G);
                 pm = AT_RELOC(g0, G);
             }
         } else {
             for (; G + 4 <= Gend; G += 4) {
-                const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+                const int4 g0 = col(G), g1 = col(G + 1), g2 = col(G + 2), g3 = col(G + 3);
                 const uint32_t p0 = AT_RELOC(g0, G), p1 = AT_RELOC(g1, G + 1);
                 const uint32_t p2 = AT_RELOC(g2, G + 2), p3 = AT_RELOC(g3, G + 3);
                 pm = ((unsigned)(G - Gi) >= 2u) ? p0 : pm;
@@ -333,7 +344,7 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
                 pm = ((unsigned)(G + 3 - Gi) >= 2u) ? min(pm, p3) : pm;
             }
             for (; G < Gend; ++G) {
-                const int4 g0 = c.gap[G];
+                const int4 g0 = col(G);
                 const uint32_t p0 = AT_RELOC(g0, G);
                 pm = ((unsigned)(G - Gi) >= 2u) ? p0 : pm;
             }
