@@ -101,8 +101,11 @@ __host__ __device__ inline WLay wave_layout(int M, int V, int R, int Cs, int esz
 
 template <typename TE>
 struct W {
-    TE *tc[2];
-    int32_t *mrow, *mcol, *vrow, *vcol, *svc[2], *w, *heli, *vtype, *cost;
+    // the two vehicle types' travel blocks and loaded legs: picked by a select,
+    // never by an index, so the struct stays in registers
+    TE *tc0, *tc1;
+    int32_t *svc0, *svc1;
+    int32_t *mrow, *mcol, *vrow, *vcol, *w, *heli, *vtype, *cost;
     int32_t *seq, *off, *rt, *pof, *rof, *tabu;
     int32_t *gx, *gy, *gv, *glv, *glat, *gc;
     int32_t *mx, *my, *mlv, *mlat, *mout, *mrem, *mok;
@@ -111,7 +114,9 @@ struct W {
     int M, V, H, FL;
     bool useW, useH, useFL;   // time limits, helicopter-only missions, flight limit
 
-    __device__ int tv(int v, int x) const { return (int)tc[vtype[v]][x]; }
+    __device__ TE *tcp(int ty) const { return ty ? tc1 : tc0; }
+    __device__ int32_t *svcp(int ty) const { return ty ? svc1 : svc0; }
+    __device__ int tv(int v, int x) const { return (int)tcp(vtype[v])[x]; }
 };
 
 template <typename TE>
@@ -119,12 +124,12 @@ __device__ W<TE> make_w(char *base, const WLay &l, const InstDev &I)
 {
     W<TE> c;
     const bool two = I.T2 != nullptr;
-    c.tc[0] = (TE *)(base + l.tc0);
-    c.tc[1] = two ? (TE *)(base + l.tc1) : c.tc[0];
+    c.tc0 = (TE *)(base + l.tc0);
+    c.tc1 = two ? (TE *)(base + l.tc1) : c.tc0;
     c.mrow = (int32_t *)(base + l.mrow); c.mcol = (int32_t *)(base + l.mcol);
     c.vrow = (int32_t *)(base + l.vrow); c.vcol = (int32_t *)(base + l.vcol);
-    c.svc[0] = (int32_t *)(base + l.svc0);
-    c.svc[1] = two ? (int32_t *)(base + l.svc1) : c.svc[0];
+    c.svc0 = (int32_t *)(base + l.svc0);
+    c.svc1 = two ? (int32_t *)(base + l.svc1) : c.svc0;
     c.w = (int32_t *)(base + l.w); c.heli = (int32_t *)(base + l.heli);
     c.vtype = (int32_t *)(base + l.vtype); c.cost = (int32_t *)(base + l.cost);
     c.seq = (int32_t *)(base + l.seq); c.off = (int32_t *)(base + l.off);
@@ -161,17 +166,17 @@ __device__ int stage(const InstDev &I, const W<TE> &c, int lane)
             int x = 0;
             if (col < C) x = Ts[k][(int64_t)I.exit_loc[r] * L + I.enter_loc[col]];
             if (x < 0 || x >= kMaxTravel) bad = AT_ERANGE;
-            c.tc[k][e] = (TE)x;
+            c.tcp(k)[e] = (TE)x;
         }
     for (int m = lane; m < M; m += kWave) {
         c.mrow[m] = I.mrow[m];
         c.mcol[m] = I.mcol[m];
         const int64_t pd = (int64_t)I.p[m] * L + I.d[m];
-        c.svc[0][m] = I.T[pd];
+        c.svc0[m] = I.T[pd];
         if (I.T2) {
             const int x = I.T2[pd];
             if (x < 0 || x >= kMaxTravel) bad = AT_ERANGE;
-            c.svc[1][m] = x;
+            c.svc1[m] = x;
         }
         const int wm = I.w ? I.w[m] : 0;
         const int hm = I.heli ? I.heli[m] : 0;
@@ -200,8 +205,8 @@ __device__ void prep(const W<TE> &c, int Mp, int lane)
 {
     for (int i = lane; i < Mp; i += kWave) {
         const int m = c.seq[i], r = c.rt[i], ty = c.vtype[r];
-        const TE *tc = c.tc[ty];
-        const int32_t *svc = c.svc[ty];
+        const TE *tc = c.tcp(ty);
+        const int32_t *svc = c.svcp(ty);
         const bool first = i == c.off[r], last = i + 1 == c.off[r + 1];
         const int pm = first ? -1 : c.seq[i - 1], nm = last ? -1 : c.seq[i + 1];
         const int x = first ? c.vrow[r] : c.mrow[pm];
@@ -227,16 +232,16 @@ __device__ void prep(const W<TE> &c, int Mp, int lane)
         c.gx[G] = x; c.gy[G] = c.vcol[r]; c.gv[G] = r;
         c.glv[G] = (empty || !c.useW) ? 0 : c.w[lm];
         c.glat[G] = c.H;
-        c.gc[G] = (int)c.tc[ty][x + c.vcol[r]];
+        c.gc[G] = (int)c.tcp(ty)[x + c.vcol[r]];
         if (c.useFL) {
             // the route's flight time in its own matrix
             int s = 0, prevx = c.vrow[r];
             for (int k = c.off[r]; k < e; ++k) {
                 const int m = c.seq[k];
-                s += (int)c.tc[ty][prevx + c.mcol[m]] + c.svc[ty][m];
+                s += (int)c.tcp(ty)[prevx + c.mcol[m]] + c.svcp(ty)[m];
                 prevx = c.mrow[m];
             }
-            if (!empty) s += (int)c.tc[ty][prevx + c.vcol[r]];
+            if (!empty) s += (int)c.tcp(ty)[prevx + c.vcol[r]];
             c.cost[r] = s;
         }
     }
@@ -248,8 +253,8 @@ template <typename TE>
 __device__ __forceinline__ bool relocate_eval(const W<TE> &c, int m, int G, int &d)
 {
     const int v = c.gv[G], ty = c.vtype[v], src = c.rof[m];
-    const TE *tc = c.tc[ty];
-    const int sv = c.svc[ty][m];
+    const TE *tc = c.tcp(ty);
+    const int sv = c.svcp(ty)[m];
     const int tAX = (int)tc[c.gx[G] + c.mcol[m]], tXB = (int)tc[c.mrow[m] + c.gy[G]];
     const int ins = tAX + tXB - c.gc[G] + sv;
     d = c.mrem[m] + ins;
@@ -276,8 +281,8 @@ __device__ __forceinline__ bool swap_eval(const W<TE> &c, int a, int b, int &d)
     if (ra == rb && (pb == pa + 1 || pa == pb + 1)) {
         const int F = pa < pb ? a : b, S = pa < pb ? b : a;
         const int ty = c.vtype[ra];
-        const TE *tc = c.tc[ty];
-        const int32_t *svc = c.svc[ty];
+        const TE *tc = c.tcp(ty);
+        const int32_t *svc = c.svcp(ty);
         const int tPS = (int)tc[c.mx[F] + c.mcol[S]], tSF = (int)tc[c.mrow[S] + c.mcol[F]];
         const int tFN = (int)tc[c.mrow[F] + c.my[S]], tFS = (int)tc[c.mrow[F] + c.mcol[S]];
         d = tPS + tSF + tFN + svc[S] + svc[F] - (c.mout[F] + c.mout[S] - tFS);
@@ -288,10 +293,10 @@ __device__ __forceinline__ bool swap_eval(const W<TE> &c, int a, int b, int &d)
         return true;
     }
     const int ta = c.vtype[ra], tb = c.vtype[rb];
-    const TE *tca = c.tc[ta], *tcb = c.tc[tb];
+    const TE *tca = c.tcp(ta), *tcb = c.tcp(tb);
     const int tPb = (int)tca[c.mx[a] + c.mcol[b]], tbN = (int)tca[c.mrow[b] + c.my[a]];
     const int tPa = (int)tcb[c.mx[b] + c.mcol[a]], taN = (int)tcb[c.mrow[a] + c.my[b]];
-    const int sb = c.svc[ta][b], sa = c.svc[tb][a];
+    const int sb = c.svcp(ta)[b], sa = c.svcp(tb)[a];
     const int da = tPb + tbN + sb - c.mout[a], db = tPa + taN + sa - c.mout[b];
     d = da + db;
     if (c.useH && ((c.heli[b] && ta == 1) || (c.heli[a] && tb == 1))) return false;
@@ -519,10 +524,10 @@ __device__ int64_t objective(const W<TE> &c, int lane)
         int prevx = c.vrow[r];
         for (int k = c.off[r]; k < e; ++k) {
             const int m = c.seq[k];
-            s += (int64_t)c.tc[ty][prevx + c.mcol[m]] + c.svc[ty][m];
+            s += (int64_t)c.tcp(ty)[prevx + c.mcol[m]] + c.svcp(ty)[m];
             prevx = c.mrow[m];
         }
-        s += (int64_t)c.tc[ty][prevx + c.vcol[r]];
+        s += (int64_t)c.tcp(ty)[prevx + c.vcol[r]];
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor((long long)s, o, 64);
     return s;
@@ -573,13 +578,13 @@ __device__ int greedy(const W<TE> &c, uint64_t seed, int lane)
             for (int v = lane; v < V; v += kWave) {
                 const int ty = c.vtype[v];
                 if (c.useH && c.heli[m] && ty == 1) continue;
-                const TE *tc = c.tc[ty];
+                const TE *tc = c.tcp(ty);
                 const int e = c.off[v + 1];
                 const bool empty = c.off[v] == e;
                 const int lm = empty ? -1 : c.seq[e - 1];
                 const int x = empty ? c.vrow[v] : c.mrow[lm];
                 const int lv = (empty || !c.useW) ? 0 : c.w[lm];
-                const int sv = c.svc[ty][m];
+                const int sv = c.svcp(ty)[m];
                 const int tLX = (int)tc[x + c.mcol[m]], tXB = (int)tc[c.mrow[m] + c.vcol[v]];
                 const int add = tLX + sv + tXB - (int)tc[x + c.vcol[v]];
                 if (c.useW && (lv + tLX + sv > c.w[m] || c.w[m] + tXB > c.H)) continue;

@@ -213,3 +213,31 @@ def test_mixed_tabu_widths_resume_in_chunks():
     for k, t in enumerate(tickets):
         _same(alone[k], got[t], f"request {k}")
     srv.close()
+
+
+def test_many_short_hbm_resident_requests_share_the_queue():
+    """Hundreds of short requests too large for one workgroup's LDS (HBM-resident)
+    beside a long one: a launch cannot give each its own workgroups, so the short
+    ones run to their end on the workers' queue while the long one keeps its own
+    workgroups over several launches; every result equals the request alone, and
+    two equal the oracle's."""
+    big = make_instance(901, 1350, 23, 45, 900)
+    reqs = [(big, dict(variant=at.AT_TABU, tenure=11, iters=200, restart_seed=3, trace=True))]
+    for k in range(260):
+        # 100 vehicles: the tabu table alone takes 60 KB of LDS, so the solve is HBM-resident
+        inst = make_instance(5000 + k, 450, 10, 100, 300)
+        reqs.append((inst, dict(variant=at.AT_TABU if k % 4 else at.AT_NS, tenure=7, iters=30,
+                                restart_seed=k, trace=True)))
+    devs = [_dev(i) for i, _ in reqs]
+    alone = [at.solve(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    srv = at.Server(8 << 30, max_slots=512, chunk_iters=25)
+    tickets = [srv.submit(d, **kw) for d, (_, kw) in zip(devs, reqs)]
+    got = _drive(srv, list(tickets))
+    for k, t in enumerate(tickets):
+        _same(alone[k], got[t], f"request {k}")
+    srv.close()
+    for k in (1, 2):
+        inst, kw = reqs[k]
+        _, o = oracle_solve(inst, variant=kw["variant"], tenure=kw["tenure"], iters=kw["iters"],
+                            restart_seed=kw["restart_seed"])
+        assert_same_result(o, alone[k], f"short HBM-resident request {k} vs oracle")
