@@ -950,7 +950,7 @@ __device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int la
 }
 
 template <typename TE, typename TB, bool MULTI, bool WAVE = false>
-__device__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
+__device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 {
     const InstDev &I = *J.inst;
     // WAVE: one wavefront runs the solve in its own LDS region
@@ -1675,7 +1675,7 @@ __device__ __forceinline__ bool ring_tabu(const int4 *ring, int n, int r1, int m
 }
 
 template <typename TE, typename TB>
-__device__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uint64_t *red)
+__device__ __forceinline__ void run_job_global(const JobDev &J, int wg, int nwg, char *smem, uint64_t *red)
 {
     const InstDev &I = *J.inst;
     GlobalBufs &B = *J.gb;

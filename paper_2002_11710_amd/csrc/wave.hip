@@ -248,7 +248,8 @@ __device__ void prep(const W<TE> &c, int Mp, int lane)
     wsync();
 }
 
-// Delta and feasibility of relocating mission m into gap G.
+// Delta and feasibility of relocating mission m into gap G.  The conditions are
+// combined without branches, so the loads of consecutive slots can overlap.
 template <typename TE>
 __device__ __forceinline__ bool relocate_eval(const W<TE> &c, int m, int G, int &d)
 {
@@ -258,19 +259,17 @@ __device__ __forceinline__ bool relocate_eval(const W<TE> &c, int m, int G, int 
     const int tAX = (int)tc[c.gx[G] + c.mcol[m]], tXB = (int)tc[c.mrow[m] + c.gy[G]];
     const int ins = tAX + tXB - c.gc[G] + sv;
     d = c.mrem[m] + ins;
-    if (c.useH && c.heli[m] && ty == 1) return false;
+    bool ok = true;
+    if (c.useH) ok &= !(c.heli[m] != 0 && ty == 1);
     if (c.useW) {
         const int wm = c.w[m];
-        if (!c.mok[m] || c.glv[G] + tAX + sv > wm || wm + tXB > c.glat[G]) return false;
+        ok &= (c.mok[m] != 0) & (c.glv[G] + tAX + sv <= wm) & (wm + tXB <= c.glat[G]);
     }
     if (c.useFL) {
-        if (v == src) {
-            if (c.cost[v] + d > c.FL) return false;
-        } else if (c.cost[src] + c.mrem[m] > c.FL || c.cost[v] + ins > c.FL) {
-            return false;
-        }
+        const int cv = c.cost[v], cs = c.cost[src];
+        ok &= v == src ? cv + d <= c.FL : (cs + c.mrem[m] <= c.FL) & (cv + ins <= c.FL);
     }
-    return true;
+    return ok;
 }
 
 // Delta and feasibility of swapping missions a and b.
@@ -326,21 +325,35 @@ __device__ uint64_t eval_best(const W<TE> &c, int lane, int t, int thr, bool use
     const int M = c.M, V = c.V, NG = M + V;
     const uint32_t R = (uint32_t)M * (uint32_t)NG;
     uint64_t best = kKeyNone;
-    // relocates: slot m*NG + G, lanes over consecutive slots
+    // relocates: slot m*NG + G, lanes over consecutive slots, two slots of a lane
+    // per step (their loads in flight together)
     int m = 0, G = lane;
     while (G >= NG && m < M) { G -= NG; ++m; }
-    for (; m < M;) {
-        const int s = c.pof[m] + c.rof[m];
-        uint64_t k = kKeyNone;
+    auto reloc_key = [&](int mm, int GG) {
+        const int s = c.pof[mm] + c.rof[mm];
         int d;
-        if ((unsigned)(G - s) >= 2u && relocate_eval(c, m, G, d)) {
-            const bool tb = use_tabu && c.tabu[c.gv[G] * M + m] > t;
-            k = key_of(tb && !(d < thr), d, (uint32_t)m * (uint32_t)NG + (uint32_t)G);
-        }
-        if (keys) keys[(uint32_t)m * (uint32_t)NG + (uint32_t)G] = k;
-        best = k < best ? k : best;
+        const bool ok = relocate_eval(c, mm, GG, d);
+        const bool tb = use_tabu && c.tabu[c.gv[GG] * M + mm] > t;
+        return ((unsigned)(GG - s) >= 2u && ok) ? key_of(tb && !(d < thr), d, (uint32_t)mm * (uint32_t)NG + (uint32_t)GG)
+                                                 : kKeyNone;
+    };
+    while (m < M) {
+        const int m1 = m, G1 = G;
         G += kWave;
         while (G >= NG && m < M) { G -= NG; ++m; }
+        const bool two = m < M;
+        const int m2 = two ? m : m1, G2 = two ? G : G1;
+        const uint64_t k1 = reloc_key(m1, G1), k2 = reloc_key(m2, G2);
+        if (keys) {
+            keys[(uint32_t)m1 * (uint32_t)NG + (uint32_t)G1] = k1;
+            if (two) keys[(uint32_t)m2 * (uint32_t)NG + (uint32_t)G2] = k2;
+        }
+        best = k1 < best ? k1 : best;
+        best = (two && k2 < best) ? k2 : best;
+        if (two) {
+            G += kWave;
+            while (G >= NG && m < M) { G -= NG; ++m; }
+        }
     }
     // swaps: slot R + a*M - a(a+1)/2 + (b-a-1), lanes over consecutive slots
     const int64_t nsw = (int64_t)M * (M - 1) / 2;
