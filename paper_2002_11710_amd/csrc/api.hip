@@ -378,26 +378,80 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     if (!h.chunked && h.pr.schedule == AT_SCHED_AUTO && pick_wave(h.slots) &&
         lds_layout(d.M, d.V, d.R, d.Cs, d.esz, tabu_bytes(h.pr)).total <= kLdsLimit / 2)
         return plan_wave(h, d);
-    if (alone && (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= 20000))) {
-        // measured on gfx950 (16 x 400 missions): 512 threads, 8-column swap units
-        // (16-column relocate units), one wavefront per work unit (the iteration
-        // waits for the wavefront with the most work), up to 96 workgroups (more
-        // slots to poll cost more than the eval saves)
-        if (!h.pr.block) h.block = 512;
-        if (!h.pr.chunk) h.chunk = 8;
-        h.rchunk = std::min(64, 2 * h.chunk);
-        const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
-        int64_t units = 0;
-        for (int64_t jb = 0; jb < d.M; jb += kWave)
-            units += (d.M + d.V + h.rchunk - 1) / h.rchunk + (d.M - jb + h.chunk - 1) / h.chunk;
-        const int64_t waves = std::max(1, h.block / kWave);
-        int g = h.pr.n_groups ? h.pr.n_groups
-                              : (int)std::max<int64_t>(1, std::min<int64_t>(96, (units + waves - 1) / waves));
-        g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
-        if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
-        h.kind = AT_SCHED_MULTI;
-        h.groups = g;
+    if (alone && multi_eligible(h)) return plan_multi(h, d);
+    return AT_OK;
+}
+
+// Whether a solve planned on one workgroup may run on the multi-workgroup
+// schedule instead: asked for it, or large enough under AUTO.
+bool multi_eligible(const JobHost &h)
+{
+    return h.kind == AT_SCHED_WG && !h.wtile &&
+           (h.pr.schedule == AT_SCHED_MULTI || (h.pr.schedule == AT_SCHED_AUTO && h.slots >= kMultiMinSlots));
+}
+
+// The multi-workgroup plan of a solve whose state fits one workgroup's LDS:
+// measured on gfx950 (16 x 400 missions): 512 threads, 8-column swap units
+// (16-column relocate units), one wavefront per work unit (the iteration waits
+// for the wavefront with the most work), up to 96 workgroups (more slots to poll
+// cost more than the eval saves).  One solve alone: workgroups [0, groups),
+// slot set 0.
+int plan_multi(JobHost &h, const InstDev &d)
+{
+    if (!h.pr.block) h.block = 512;
+    if (!h.pr.chunk) h.chunk = 8;
+    h.rchunk = std::min(64, 2 * h.chunk);
+    const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
+    int64_t units = 0;
+    for (int64_t jb = 0; jb < d.M; jb += kWave)
+        units += (d.M + d.V + h.rchunk - 1) / h.rchunk + (d.M - jb + h.chunk - 1) / h.chunk;
+    const int64_t waves = std::max(1, h.block / kWave);
+    int g = h.pr.n_groups ? h.pr.n_groups
+                          : (int)std::max<int64_t>(1, std::min<int64_t>(96, (units + waves - 1) / waves));
+    g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
+    if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
+    h.kind = AT_SCHED_MULTI;
+    h.groups = g;
+    h.g0 = 0;
+    h.mx = 0;
+    h.launch = 0;
+    return AT_OK;
+}
+
+// A batch of at most kMaxMultiJobs solves, each large and fitting one
+// workgroup's LDS (all of one entry and tabu width): one cooperative launch of
+// the multi-workgroup schedule runs them side by side, each on its own range of
+// workgroups and its own slot set; a workgroup per solve would leave most of the
+// GPU idle.  Each asks for what it would take alone; when the sum exceeds what
+// the GPU holds, the shares shrink in proportion (at least one each).  Leaves
+// the jobs as they are when the batch does not qualify.
+int plan_multi_batch(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih)
+{
+    const int n = (int)jobs.size();
+    if (n < 2 || n > kMaxMultiJobs) return AT_OK;
+    for (const JobHost &h : jobs)
+        if (!multi_eligible(h) || h.tb16 != jobs[0].tb16 || h.esz16 != jobs[0].esz16) return AT_OK;
+    std::vector<JobHost> m = jobs;
+    uint32_t lds = 0;
+    int64_t want = 0;
+    for (JobHost &h : m) {
+        int rc = plan_multi(h, ih[(size_t)h.inst]);
+        if (rc) return rc;
+        if (h.block != m[0].block) return AT_OK;
+        lds = std::max(lds, h.lds);
+        want += h.groups;
     }
+    const int cap = max_groups_multi(m[0].block, lds, m[0].tb16, m[0].esz16);
+    if (cap < n) return AT_OK;
+    int g0 = 0;
+    for (int k = 0; k < n; ++k) {
+        JobHost &h = m[(size_t)k];
+        if (want > cap) h.groups = std::max(1, (int)((int64_t)h.groups * cap / want));
+        h.g0 = g0;
+        h.mx = k;
+        g0 += h.groups;
+    }
+    jobs.swap(m);
     return AT_OK;
 }
 
@@ -437,6 +491,7 @@ int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal
     j.g0 = h.g0;
     j.ng = h.groups;
     j.sched = h.kind;
+    j.mx = h.mx;
     return AT_OK;
 }
 
@@ -598,11 +653,22 @@ int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order,
             // the global jobs, which come last: one cooperative launch per group of them
             return launch_globals(k, s);
         }
-        if ((e = fill_u64(&xs->slots[0][0], 1ull << 63, 2 * kMaxGroups * kSlotStride, s)) != hipSuccess)
+        // the multi-workgroup solves planned into one launch (consecutive, slot sets 0..)
+        int e1 = k, groups = 0;
+        uint32_t lds = 0;
+        while (e1 < n && e1 - k < kMaxMultiJobs && jobs[(size_t)order[(size_t)e1]].kind == AT_SCHED_MULTI &&
+               jobs[(size_t)order[(size_t)e1]].launch == hf.launch && jobs[(size_t)order[(size_t)e1]].mx == e1 - k) {
+            const JobHost &h = jobs[(size_t)order[(size_t)e1]];
+            groups = std::max(groups, h.g0 + h.groups);
+            lds = std::max(lds, h.lds);
+            ++e1;
+        }
+        if ((e = fill_u64(&xs->slots[0][0][0], 1ull << 63, (size_t)(e1 - k) * 2 * kMaxGroups * kSlotStride, s)) !=
+            hipSuccess)
             return hip_fail(e, "reset exchange");
-        e = launch_search_multi(dj + k, xs, hf.groups, hf.block, hf.lds, hf.tb16, hf.esz16, s);
+        e = launch_search_multi(dj + k, e1 - k, xs, groups, hf.block, lds, hf.tb16, hf.esz16, s);
         if (e != hipSuccess) return hip_fail(e, "cooperative search launch");
-        ++k;
+        k = e1;
     }
     return AT_OK;
 }
@@ -621,6 +687,9 @@ std::vector<int> order_jobs(const std::vector<JobHost> &jobs)
         auto grp = [](int kind) { return kind == AT_SCHED_WAVE ? 0 : kind == AT_SCHED_WG ? 1 : kind; };
         const int cx = grp(x.kind), cy = grp(y.kind);
         if (cx != cy) return cx < cy;
+        // multi-workgroup solves of one launch in the order of their workgroup ranges
+        // (the kernel finds a workgroup's solve by binary search over them)
+        if (x.kind == AT_SCHED_MULTI) return x.g0 < y.g0;
         if (x.kind == AT_SCHED_WG || x.kind == AT_SCHED_GLOBAL || x.kind == AT_SCHED_WAVE) {
             const int kx = ((x.wtile * 2 + x.esz16) * 2 + x.tb16) * 4096 + x.block;
             const int ky = ((y.wtile * 2 + y.esz16) * 2 + y.tb16) * 4096 + y.block;
@@ -726,7 +795,9 @@ static int run_jobs(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, 
         if (rc) return rc;
         h.iters = h.pr.max_iters;
     }
-    int rc = upload_gstates(jobs, ih, s);
+    int rc = plan_multi_batch(jobs, ih);
+    if (rc) return rc;
+    rc = upload_gstates(jobs, ih, s);
     if (rc) return rc;
     const std::vector<int> order = order_jobs(jobs);
     if ((rc = assign_groups(jobs, order)) != AT_OK) return rc;

@@ -57,6 +57,7 @@ constexpr int kMaxGroups = 256;               // workgroups of one cooperative s
 // 46 workgroups takes 1.6 us with contiguous slots, 1.0 us with one per line).
 constexpr int kSlotStride = 16;
 constexpr int kMaxClasses = 16;               // concurrent one-workgroup-per-job launches
+constexpr int kMaxMultiJobs = 8;              // multi-workgroup solves sharing one launch
 
 struct InstDev {
     // filled by the host
@@ -139,8 +140,9 @@ struct JobDev {
     int32_t rchunk;                   // gaps per relocate work unit
     int32_t form;                     // AT_FORM_BEST or AT_FORM_SWEEP (wave schedule)
     int32_t gk;                       // global schedule: missions staged per block
-    int32_t g0, ng;                   // global schedule: the solve's workgroups in the launch
+    int32_t g0, ng;                   // global / multi schedules: the solve's workgroups in the launch
     int32_t sched;                    // AT_SCHED_* the solve runs on
+    int32_t mx;                       // multi schedule: the solve's argmin slot set in Xchg
     uint64_t seed;
     int32_t *out_off, *out_seq, *out_of;
     int32_t *fin_off, *fin_seq;       // routes after the last iteration (may be null)
@@ -156,9 +158,10 @@ struct JobDev {
 // Device-side scheduling state of a call (the global schedule keeps its own in
 // each solve's GlobalBufs).
 struct Xchg {
-    // per-workgroup argmin slots of the multi-workgroup schedule, double-buffered by
-    // iteration parity; bit 63 carries the iteration's tag (bit 1 of the iteration)
-    uint64_t slots[2][kMaxGroups * kSlotStride];   // slot of workgroup w at w * kSlotStride
+    // per-workgroup argmin slots of the multi-workgroup schedule, one set per solve of
+    // a launch, double-buffered by iteration parity; bit 63 carries the iteration's tag
+    // (bit 1 of the iteration)
+    uint64_t slots[kMaxMultiJobs][2][kMaxGroups * kSlotStride];   // workgroup w at w * kSlotStride
     uint32_t queues[kMaxClasses];     // next job of each one-workgroup-per-job launch
 };
 
@@ -240,7 +243,9 @@ hipError_t launch_search_wg(const JobDev *jobs, int32_t n_jobs, uint32_t *queue,
 hipError_t launch_search_wg_wave(const JobDev *jobs, int32_t n_jobs, uint32_t *queue, int grid,
                                  int waves_per_group, uint32_t lds_per_solve, int tb16, int esz16,
                                  hipStream_t s);
-hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
+// The multi-workgroup solves jobs[0..n_jobs) in one cooperative launch, each on its
+// range [g0, g0 + ng) of the n_groups workgroups, with its own slot set (mx).
+hipError_t launch_search_multi(const JobDev *jobs, int n_jobs, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);
 hipError_t launch_search_global(const JobDev *jobs, int n_jobs, int n_groups, int block,
                                 uint32_t lds_bytes, int tb16, int esz16, hipStream_t s);

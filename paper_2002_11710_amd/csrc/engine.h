@@ -31,7 +31,8 @@ struct JobHost {
     int kind = AT_SCHED_WG;           // AT_SCHED_WG, AT_SCHED_MULTI or AT_SCHED_GLOBAL
     int gk = 0, gkmax = 0;            // global schedule: missions staged per block (chosen, LDS limit)
     int dM = 0, dV = 0, dR = 0, dC = 0, desz = 4;   // instance sizes (global schedule LDS plan)
-    int g0 = 0, launch = 0;           // global schedule: first workgroup, launch index (assign_groups)
+    int g0 = 0, launch = 0;           // global / multi schedules: first workgroup, launch index
+    int mx = 0;                       // multi schedule: slot set in the launch
     GlobalBufs *gstate = nullptr;     // reserved HBM state (global schedule)
     bool chunked = false;             // run in chunks of iterations (serving): no wave schedule
     bool wtile = false;               // wave schedule on the one-workgroup code (unconstrained best form)
@@ -52,6 +53,12 @@ int prepare_enqueue(int32_t n_inst, InstDev *dev, InstDev *host, hipStream_t s);
 int prepare_check(int32_t n_inst, const InstDev *host);
 int prepare_instances(int32_t n_inst, InstDev *dev, std::vector<InstDev> &host, hipStream_t s);
 int plan_job(JobHost &h, const InstDev &d, bool alone);
+// Solves at or above this many move slots take the multi-workgroup schedule
+// under AUTO when they are alone in their call (or in a small batch).
+constexpr int64_t kMultiMinSlots = 20000;
+bool multi_eligible(const JobHost &h);
+int plan_multi(JobHost &h, const InstDev &d);
+int plan_multi_batch(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih);
 int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal);
 int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s);
 int launch_jobs(const std::vector<JobHost> &jobs, const std::vector<int> &order, JobDev *dj,

@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 // never confuse iterations t and t+2.
                 const int rel = t - J.t_begin;
                 const uint64_t tag = (uint64_t)((rel >> 1) & 1);
-                uint64_t *slots = xs->slots[rel & 1];
+                uint64_t *slots = xs->slots[J.mx][rel & 1];
                 if (lane == 0)
                     __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1954,10 +1954,18 @@ __global__ void __launch_bounds__(256) k_search_wg_wave(const JobDev *jobs, int 
 }
 
 template <typename TE, typename TB>
-__global__ void __launch_bounds__(1024) k_search_multi(const JobDev *job, Xchg *xs)
+__global__ void __launch_bounds__(1024) k_search_multi(const JobDev *jobs, int n_jobs, Xchg *xs)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    run_job<TE, TB, true>(*job, smem, (int)blockIdx.x, (int)gridDim.x, xs);
+    // the solve whose workgroup range holds this workgroup
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].g0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const JobDev &J = jobs[lo];
+    run_job<TE, TB, true>(J, smem, b - J.g0, J.ng, xs);
 }
 
 // Test hook: every slot's key for a given state (keys[0..n_slots)), and the
@@ -2058,23 +2066,23 @@ hipError_t launch_search_wg_wave(const JobDev *jobs, int32_t n_jobs, uint32_t *q
 }
 
 template <typename TE, typename TB>
-static hipError_t coop_launch(const JobDev *job, Xchg *xs, int n_groups, int block,
+static hipError_t coop_launch(const JobDev *jobs, int n_jobs, Xchg *xs, int n_groups, int block,
                               uint32_t lds_bytes, hipStream_t s)
 {
     hipError_t e = set_lds(k_search_multi<TE, TB>, lds_bytes);
     if (e != hipSuccess) return e;
-    void *args[] = {(void *)&job, (void *)&xs};
+    void *args[] = {(void *)&jobs, (void *)&n_jobs, (void *)&xs};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_search_multi<TE, TB>),
                                       dim3(n_groups), dim3(block), args, lds_bytes, s);
 }
 
-hipError_t launch_search_multi(const JobDev *job, Xchg *xs, int n_groups, int block,
+hipError_t launch_search_multi(const JobDev *jobs, int n_jobs, Xchg *xs, int n_groups, int block,
                                uint32_t lds_bytes, int tb16, int esz16, hipStream_t s)
 {
-    if (esz16 && tb16) return coop_launch<uint16_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
-    if (esz16) return coop_launch<uint16_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
-    if (tb16) return coop_launch<int32_t, uint16_t>(job, xs, n_groups, block, lds_bytes, s);
-    return coop_launch<int32_t, int32_t>(job, xs, n_groups, block, lds_bytes, s);
+    if (esz16 && tb16) return coop_launch<uint16_t, uint16_t>(jobs, n_jobs, xs, n_groups, block, lds_bytes, s);
+    if (esz16) return coop_launch<uint16_t, int32_t>(jobs, n_jobs, xs, n_groups, block, lds_bytes, s);
+    if (tb16) return coop_launch<int32_t, uint16_t>(jobs, n_jobs, xs, n_groups, block, lds_bytes, s);
+    return coop_launch<int32_t, int32_t>(jobs, n_jobs, xs, n_groups, block, lds_bytes, s);
 }
 
 template <typename TE, typename TB>

@@ -429,3 +429,37 @@ def test_flat_batch_marshalling_equals_list():
         assert np.array_equal(flat.route_of(k).cpu().numpy(), r["route_of"])
         assert np.array_equal(flat.final_off(k).cpu().numpy(), r["final_off"])
         assert np.array_equal(flat.final_seq(k).cpu().numpy(), r["final_seq"])
+
+
+def test_small_batch_of_large_solves_shares_one_multi_launch():
+    """A batch of a few large LDS-resident solves runs them side by side on the
+    multi-workgroup schedule, each on its own workgroup range and slot set: the
+    Tabu and NS solves of the 16 x 400 workload, and three restarts of one
+    instance, each equal to its oracle run."""
+    from gen.instances import restart_seed
+    inst = m400_instance(0)
+    dev = _dev(inst)
+    params = [at._capi.make_params(at.AT_TABU, 15, 300, True, 0, True),
+              at._capi.make_params(at.AT_NS, 15, 300, True, 0, True)]
+    res = at.solve_batch([dev, dev], params, 1)
+    for k, variant in enumerate((at.AT_TABU, at.AT_NS)):
+        _, o = oracle_solve(inst, variant=variant, tenure=15, iters=300)
+        assert_same_result(o, res[k], f"Tabu + NS batch, solve {k}")
+    inst2 = make_instance(77, 450, 9, 18, 300)
+    res = at.solve_batch([_dev(inst2)], [at._capi.make_params(at.AT_TABU, 9, 120, True, 41, True)], 3)
+    for r in range(3):
+        _, o = oracle_solve(inst2, tenure=9, iters=120, restart_seed=restart_seed(41, r))
+        assert_same_result(o, res[r], f"restart batch, restart {r}")
+
+
+def test_batch_of_many_large_solves_keeps_one_workgroup_each():
+    """More large solves than one multi-workgroup launch takes: each keeps one
+    workgroup, and equals the solve alone."""
+    insts = [make_instance(900 + k, 300, 8, 12, 180) for k in range(9)]
+    devs = [_dev(i) for i in insts]
+    params = [at._capi.make_params(at.AT_TABU, 7, 25, True, 0, True) for _ in insts]
+    res = at.solve_batch(devs, params, 1)
+    for k, d in enumerate(devs):
+        alone = at.solve(d, tenure=7, iters=25)
+        assert np.array_equal(gpu_to_np(res[k])["tr_move"], gpu_to_np(alone)["tr_move"]), k
+        assert res[k]["best_obj"] == alone["best_obj"], k
