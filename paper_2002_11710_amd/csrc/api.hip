@@ -443,10 +443,25 @@ int plan_multi_batch(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih)
     }
     const int cap = max_groups_multi(m[0].block, lds, m[0].tb16, m[0].esz16);
     if (cap < n) return AT_OK;
+    if (want > cap) {
+        // scale to the co-resident limit; the floor of 1 can overshoot it by a few groups,
+        // which come off the largest jobs (cap >= n, so every job keeps one)
+        int64_t sum = 0;
+        for (JobHost &h : m) {
+            h.groups = std::max(1, (int)((int64_t)h.groups * cap / want));
+            sum += h.groups;
+        }
+        while (sum > cap) {
+            JobHost *big = &m[0];
+            for (JobHost &h : m)
+                if (h.groups > big->groups) big = &h;
+            --big->groups;
+            --sum;
+        }
+    }
     int g0 = 0;
     for (int k = 0; k < n; ++k) {
         JobHost &h = m[(size_t)k];
-        if (want > cap) h.groups = std::max(1, (int)((int64_t)h.groups * cap / want));
         h.g0 = g0;
         h.mx = k;
         g0 += h.groups;
