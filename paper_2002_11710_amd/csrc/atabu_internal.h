@@ -311,6 +311,25 @@ int num_cus();
 hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 
+// The pair (m1 < m2) of swap number sp, the swaps numbered row by row (row m1
+// starts at m1*M - m1(m1+1)/2).  The row is the floor of the smaller root of
+// the row-start quadratic, (A - sqrt(A^2 - 8 sp)) / 2 with A = 2M - 1: in double
+// precision the square's argument is exact (below 2^53) and the computed root
+// is off by a few units in the last place of a value below 2^17 (far below
+// 2^-30), so the floor is off by at most one, next to a row boundary, and one
+// test each way corrects it.
+__device__ __forceinline__ void swap_pair(uint32_t sp, int M, int &m1, int &m2)
+{
+    const double A = 2.0 * (double)M - 1.0;
+    int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
+    a = max(0, min(a, M - 2));
+    auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
+    if (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
+    else if (a > 0 && rowstart(a) > (int64_t)sp) --a;
+    m1 = a;
+    m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
+}
+
 // ---------------------------------------------------------------------------
 // Wavefront minimum on the VALU's data-parallel primitives (DPP): each step is
 // one v_min_u32 whose second operand comes from another lane of the row (quad
@@ -322,6 +341,25 @@ hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 // low words among the lanes that hold it.  Every lane of the wavefront must be
 // active.
 // ---------------------------------------------------------------------------
+// The index of the calling thread's wavefront in its workgroup, as a scalar.
+// Every lane computes the same tid / 64, but the compiler cannot tell: what is
+// derived from it (a wavefront's work units, their bounds, loop counters) would
+// be held per lane, its loops run with vector counters and exec-mask updates,
+// and a lane index taken from it needs a readfirstlane at every use.
+__device__ __forceinline__ int wave_id(int tid)
+{
+    return __builtin_amdgcn_readfirstlane(tid / kWave);
+}
+
+// A value every lane of the wavefront holds alike (an instance's sizes, a job
+// index read from LDS), as a scalar.  Loads through generic pointers (the
+// instance a job points to) and from LDS count as per-lane for the compiler,
+// with the same cost for what is derived from them as above.
+__device__ __forceinline__ int uniform(int x)
+{
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
 template <int CTRL, int ROWS>
 __device__ __forceinline__ uint32_t dpp_min_step(uint32_t x)
 {

@@ -388,8 +388,8 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     uint64_t best = kKeyNone;
     int j = j0;
     while (j < j1) {
-        const int r = (int)((uint32_t)c.posB[j].z >> 16);
-        const int jend = min(j1, c.off[r + 1]);
+        const int r = __builtin_amdgcn_readfirstlane((int)((uint32_t)c.posB[j].z >> 16));
+        const int jend = __builtin_amdgcn_readfirstlane(min(j1, c.off[r + 1]));
         const bool t1 = (int)tabu[r * c.M + mi] > th;
         uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
         if (!diag) {
@@ -511,7 +511,8 @@ __device__ __forceinline__ uint64_t eval_all(const Ctx &c, const TE *tc, const T
         const int k = mine - u;
         const int jb = tl * kWave;
         if (k < nRC) {
-            const int rlo = c.rt[jb], rhi = c.rt[min(c.M, jb + kWave) - 1];
+            const int rlo = __builtin_amdgcn_readfirstlane(c.rt[jb]);
+            const int rhi = __builtin_amdgcn_readfirstlane(c.rt[min(c.M, jb + kWave) - 1]);
             const int G0 = k * RCH, G1 = min(c.NG, G0 + RCH);
             if constexpr (FLAT && sizeof(TE) == 2)
                 best = umin64(best, relocate_unit_flat<TE, TB>(c, tc, tabu, tl, G0, G1, lane, t, thr,
@@ -956,10 +957,10 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
     // WAVE: one wavefront runs the solve in its own LDS region
     const int tid = WAVE ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
     const int nthr = WAVE ? kWave : (int)blockDim.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
-    const int M = I.M, V = I.V;
-    const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), (int)sizeof(TB));
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, I.Cs);
+    const int lane = tid & (kWave - 1), wave = wave_id(tid), nwaves = nthr / kWave;
+    const int M = uniform(I.M), V = uniform(I.V), R = uniform(I.R), Cs = uniform(I.Cs);
+    const Lay ly = lds_layout(M, V, R, Cs, (int)sizeof(TE), (int)sizeof(TB));
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, Cs);
     TE *tc = (TE *)(smem + ly.tc);
     TB *tabu = (TB *)(smem + ly.tabu);
     const bool writer = !MULTI || wg == 0;
@@ -1070,14 +1071,8 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                         if (lane == 0) tabu[rs * M + m] = (TB)tval;
                     }
                 } else {
-                    const uint32_t sp = ix - c.R;
-                    const double A = 2.0 * (double)M - 1.0;
-                    int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
-                    a = max(0, min(a, M - 2));
-                    auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
-                    while (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
-                    while (a > 0 && rowstart(a) > (int64_t)sp) --a;
-                    const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
+                    int m1, m2;
+                    swap_pair(ix - c.R, M, m1, m2);
                     const int s1 = c.pof[m1], s2 = c.pof[m2];
                     const int r1 = c.rof[m1], r2 = c.rof[m2];
                     mv.kind = 2;
@@ -1241,13 +1236,13 @@ __device__ __forceinline__ Ctx global_ctx(const InstDev &I, const GlobalBufs &B,
     c.posC = B.posC[p];
     c.prank = nullptr;
     c.red = red;
-    c.M = I.M;
-    c.V = I.V;
-    c.NG = I.M + I.V;
+    c.M = uniform(I.M);
+    c.V = uniform(I.V);
+    c.NG = c.M + c.V;
     c.chunk = 0;
     c.rchunk = 0;
-    c.Cs = I.Cs;
-    c.R = (uint32_t)I.M * (uint32_t)(I.M + I.V);
+    c.Cs = uniform(I.Cs);
+    c.R = (uint32_t)c.M * (uint32_t)c.NG;
     return c;
 }
 
@@ -1365,9 +1360,9 @@ __device__ uint64_t eval_staged(const Ctx &c, const InstDev &I, const TE *tc, co
     constexpr int ES = (int)sizeof(TE);
     (void)tc;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
+    const int lane = tid & (kWave - 1), wave = wave_id(tid), nwaves = nthr / kWave;
     const int M = c.M, V = c.V, NG = c.NG, Rs = I.Rs, Cg = I.Cg;
-    const int Re = staged_rows(I.R, ES), Ce = staged_cols(I.C, ES);
+    const int Re = staged_rows(uniform(I.R), ES), Ce = staged_cols(uniform(I.C), ES);
     const int R16 = Re * ES / 16, C16 = Ce * ES / 16;   // 16-byte chunks of a staged column / row
     const int per = 2 * Re + 2 * Ce;
     const int Wm = (M + 31) >> 5;
@@ -1680,12 +1675,12 @@ __device__ __forceinline__ void run_job_global(const JobDev &J, int wg, int nwg,
     const InstDev &I = *J.inst;
     GlobalBufs &B = *J.gb;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
+    const int lane = tid & (kWave - 1), wave = wave_id(tid), nwaves = nthr / kWave;
     const int gtid = wg * nthr + tid, gthr = nwg * nthr;
-    const int M = I.M, V = I.V;
+    const int M = uniform(I.M), V = uniform(I.V);
     const TE *tc = (const TE *)I.tc;
     int4 *ring = B.ring;
-    const int ring_n = B.ring_slots, ring_len = 2 * ring_n;
+    const int ring_n = uniform(B.ring_slots), ring_len = 2 * ring_n;
     const bool writer = wg == 0;
     SolveState *st = J.st;
     uint32_t nb = 0;
@@ -1783,14 +1778,8 @@ __device__ __forceinline__ void run_job_global(const JobDev &J, int wg, int nwg,
                 }
             }
         } else {
-            const uint32_t sp = idx - c.R;
-            const double A = 2.0 * (double)M - 1.0;
-            int a = (int)floor((A - sqrt(A * A - 8.0 * (double)sp)) * 0.5);
-            a = max(0, min(a, M - 2));
-            auto rowstart = [&](int64_t x) { return x * M - x * (x + 1) / 2; };
-            while (a + 1 <= M - 2 && rowstart(a + 1) <= (int64_t)sp) ++a;
-            while (a > 0 && rowstart(a) > (int64_t)sp) --a;
-            const int m1 = a, m2 = (int)(a + 1 + ((int64_t)sp - rowstart(a)));
+            int m1, m2;
+            swap_pair(idx - c.R, M, m1, m2);
             const int s1 = c.pof[m1], s2 = c.pof[m2];
             mv.kind = 2;
             mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
@@ -1889,7 +1878,7 @@ __global__ void __launch_bounds__(kGlobalBlock) k_search_mixed(const JobDev *gjo
         if (threadIdx.x == 0)
             *s_job = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int j = *s_job;
+        const int j = __builtin_amdgcn_readfirstlane(*s_job);   // scalar: the job's fields load as scalars
         __syncthreads();
         if (j >= n_wjobs) return;
         const JobDev &J = wjobs[j];
@@ -1925,7 +1914,7 @@ __global__ void __launch_bounds__(1024) k_search_wg(const JobDev *jobs, int n_jo
         if (threadIdx.x == 0)
             s_job = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int j = s_job;
+        const int j = __builtin_amdgcn_readfirstlane(s_job);   // scalar: the job's fields load as scalars
         __syncthreads();
         if (j >= n_jobs) return;
         run_job<TE, TB, false>(jobs[j], smem, 0, 1, nullptr);
@@ -1942,12 +1931,12 @@ __global__ void __launch_bounds__(256) k_search_wg_wave(const JobDev *jobs, int 
                                                        uint32_t lds_per_solve)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id((int)threadIdx.x);
     char *base = smem + (size_t)wave * lds_per_solve;
     for (;;) {
         int j = 0;
         if (lane == 0) j = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        j = __shfl(j, 0, kWave);
+        j = __builtin_amdgcn_readfirstlane(j);   // lane 0's, as a scalar
         if (j >= n_jobs) return;
         run_job<TE, TB, false, true>(jobs[j], base, 0, 1, nullptr);
     }
@@ -1980,10 +1969,10 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     const JobDev &J = *jp;
     const InstDev &I = *J.inst;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave, nwaves = nthr / kWave;
-    const int M = I.M, V = I.V;
-    const Lay ly = lds_layout(M, V, I.R, I.Cs, (int)sizeof(TE), 4);
-    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, I.Cs);
+    const int lane = tid & (kWave - 1), wave = wave_id(tid), nwaves = nthr / kWave;
+    const int M = uniform(I.M), V = uniform(I.V), R = uniform(I.R), Cs = uniform(I.Cs);
+    const Lay ly = lds_layout(M, V, R, Cs, (int)sizeof(TE), 4);
+    const Ctx c = make_ctx(smem, ly, M, V, J.chunk, J.rchunk, Cs);
     TE *tc = (TE *)(smem + ly.tc);
     int32_t *tabu = (int32_t *)(smem + ly.tabu);
     load_instance<TE>(I, c, tc, tid, nthr);

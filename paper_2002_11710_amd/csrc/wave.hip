@@ -142,12 +142,12 @@ __device__ W<TE> make_w(char *base, const WLay &l, const InstDev &I)
     c.mrem = (int32_t *)(base + l.mrem); c.mok = (int32_t *)(base + l.mok);
     c.ord = (int32_t *)(base + l.ord); c.aux = (int32_t *)(base + l.aux);
     c.red = (int64_t *)(base + l.red);
-    c.M = I.M; c.V = I.V;
+    c.M = uniform(I.M); c.V = uniform(I.V);
     c.useW = I.w != nullptr;
     c.useH = I.heli != nullptr;
-    c.useFL = I.flimit > 0;
-    c.H = c.useW ? I.horizon : kBig;
-    c.FL = c.useFL ? I.flimit : 0x7FFFFFFF;
+    c.useFL = uniform(I.flimit) > 0;
+    c.H = c.useW ? uniform(I.horizon) : kBig;
+    c.FL = c.useFL ? uniform(I.flimit) : 0x7FFFFFFF;
     return c;
 }
 
@@ -156,7 +156,8 @@ __device__ W<TE> make_w(char *base, const WLay &l, const InstDev &I)
 template <typename TE>
 __device__ int stage(const InstDev &I, const W<TE> &c, int lane)
 {
-    const int L = I.L, R = I.R, C = I.C, Cs = I.Cs, M = I.M, V = I.V;
+    const int L = uniform(I.L), R = uniform(I.R), C = uniform(I.C), Cs = uniform(I.Cs);
+    const int M = uniform(I.M), V = uniform(I.V);
     int bad = AT_OK;
     const int32_t *Ts[2] = {I.T, I.T2 ? I.T2 : I.T};
     const int nt = I.T2 ? 2 : 1;
@@ -658,10 +659,8 @@ __device__ bool apply_best(const W<TE> &c, uint32_t idx, int t, int tenure, bool
         }
         apply_relocate(c, m, G, lane);
     } else {
-        const int64_t sp = (int64_t)(idx - R);
-        int a = 0;
-        while (a + 1 < M - 1 && (int64_t)(a + 1) * M - (int64_t)(a + 1) * (a + 2) / 2 <= sp) ++a;
-        const int b = (int)(a + 1 + (sp - ((int64_t)a * M - (int64_t)a * (a + 1) / 2)));
+        int a, b;
+        swap_pair(idx - R, M, a, b);
         const int ra = c.rof[a], rb = c.rof[b];
         if (use_tabu) {
             was = c.tabu[rb * M + a] > t || c.tabu[ra * M + b] > t;
@@ -677,7 +676,8 @@ template <typename TE>
 __device__ void run_wave_job(const JobDev &J, char *base, int lane)
 {
     const InstDev &I = *J.inst;
-    const WLay ly = wave_layout(I.M, I.V, I.R, I.Cs, (int)sizeof(TE), I.T2 != nullptr);
+    const WLay ly = wave_layout(uniform(I.M), uniform(I.V), uniform(I.R), uniform(I.Cs), (int)sizeof(TE),
+                                I.T2 != nullptr);
     const W<TE> c = make_w<TE>(base, ly, I);
     const int M = c.M, V = c.V;
     int status = stage(I, c, lane);
@@ -765,12 +765,12 @@ __global__ void __launch_bounds__(256) k_search_wave(const JobDev *jobs, int n_j
                                                     uint32_t lds_per_solve)
 {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id((int)threadIdx.x);
     char *base = smem + (size_t)wave * lds_per_solve;
     for (;;) {
         int j = 0;
         if (lane == 0) j = (int)__hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        j = __shfl(j, 0, 64);
+        j = __builtin_amdgcn_readfirstlane(j);   // lane 0's, as a scalar
         if (j >= n_jobs) return;
         run_wave_job<TE>(jobs[j], base, lane);
     }
