@@ -258,14 +258,28 @@ __device__ __forceinline__ uint64_t relocate_unit_flat(const Ctx &c, const TE *t
             tmask |= (uint64_t)((int)tabu[r * c.M + m] > t ? 1u : 0u) << (r - r0);
     }
     uint32_t pm = 0xFFFFFFFFu;
+    // the lane's own two gaps (no move) get the all-ones key: a select on the key,
+    // not on the update, keeps the column's gathers out of a branch
 #define AT_RELOC_FLAT(gv, Gv)                                                                  \
     do {                                                                                       \
         const int db_ = remb + (int)tc[(gv).x + mc] + (int)tc[mr + (gv).y] - (gv).z;           \
         const uint32_t bl_ = (uint32_t)(tmask >> (((gv).w & 0xFFFF) - r0)) & (db_ >= thrb ? 1u : 0u); \
-        const uint32_t k_ = (bl_ << 31) | ((uint32_t)db_ << 6) | (uint32_t)((Gv) - G0);        \
-        pm = ((unsigned)((Gv) - Gi) >= 2u) ? min(pm, k_) : pm;                                 \
+        const uint32_t own_ = ((unsigned)((Gv) - Gi) < 2u) ? 0xFFFFFFFFu : 0u;                 \
+        pm = min(pm, (bl_ << 31) | ((uint32_t)db_ << 6) | (uint32_t)((Gv) - G0) | own_);       \
     } while (0)
     int G = G0;
+    for (; G + 8 <= G1; G += 8) {
+        const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
+        const int4 g4 = c.gap[G + 4], g5 = c.gap[G + 5], g6 = c.gap[G + 6], g7 = c.gap[G + 7];
+        AT_RELOC_FLAT(g0, G);
+        AT_RELOC_FLAT(g1, G + 1);
+        AT_RELOC_FLAT(g2, G + 2);
+        AT_RELOC_FLAT(g3, G + 3);
+        AT_RELOC_FLAT(g4, G + 4);
+        AT_RELOC_FLAT(g5, G + 5);
+        AT_RELOC_FLAT(g6, G + 6);
+        AT_RELOC_FLAT(g7, G + 7);
+    }
     for (; G + 4 <= G1; G += 4) {
         const int4 g0 = c.gap[G], g1 = c.gap[G + 1], g2 = c.gap[G + 2], g3 = c.gap[G + 3];
         AT_RELOC_FLAT(g0, G);
@@ -385,82 +399,89 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
     const bool diag = j0 <= tl * kWave + kWave;
     const TB *tabu_ri = tabu + ri * c.M;
     const int th = use_tabu ? t : INT32_MAX;     // no entry exceeds INT32_MAX: nothing is tabu
-    uint64_t best = kKeyNone;
+    // minima over the whole unit: the ranks are the chunk's, so they order every
+    // partner of the unit as its slot index does (for a fixed lane), and the
+    // rank's mission is looked up once at the end
+    uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
     int j = j0;
     while (j < j1) {
         const int r = __builtin_amdgcn_readfirstlane((int)((uint32_t)c.posB[j].z >> 16));
         const int jend = __builtin_amdgcn_readfirstlane(min(j1, c.off[r + 1]));
         const bool t1 = (int)tabu[r * c.M + mi] > th;
-        uint32_t mF = 0xFFFFFFFFu, mT = 0xFFFFFFFFu;
-        if (!diag) {
-#define AT_SWAP(a, b)                                                                          \
+        // off_: all ones for a partner that is no move for this lane (diagonal units)
+#define AT_SWAP(a, b, dd, off_)                                                                \
     do {                                                                                       \
-        const int d_ = outb - (b).x + (int)tc[xri + (a).y] + (int)tc[(a).x + yci]              \
-                     + (int)tc[(a).z + mci] + (int)tc[mri + (a).w];                            \
         const bool tb_ = t1 | ((int)tabu_ri[(b).z & 0xFFFF] > th);                             \
         if (PACK5) {                                                                           \
-            const bool bl_ = tb_ & !(d_ < thrb);                                               \
-            mF = min(mF, (bl_ ? 0x80000000u : 0u) | ((uint32_t)d_ << 5) | ((uint32_t)(b).w & 31u)); \
+            const bool bl_ = tb_ & !((dd) < thrb);                                             \
+            mF = min(mF, (bl_ ? 0x80000000u : 0u) | ((uint32_t)(dd) << 5) | ((uint32_t)(b).w & 31u) | (off_)); \
         } else {                                                                               \
-            const uint32_t p_ = ((uint32_t)d_ << 6) | ((uint32_t)(b).w & 63u);                 \
+            const uint32_t p_ = ((uint32_t)(dd) << 6) | ((uint32_t)(b).w & 63u) | (off_);      \
             mT = tb_ ? min(mT, p_) : mT;                                                       \
             mF = tb_ ? mF : min(mF, p_);                                                       \
         }                                                                                      \
     } while (0)
+#define AT_SWAP_D(a, b) (outb - (b).x + (int)tc[xri + (a).y] + (int)tc[(a).x + yci]            \
+                         + (int)tc[(a).z + mci] + (int)tc[mri + (a).w])
+        if (!diag) {
             for (; j + 2 <= jend; j += 2) {
                 const int4 a0 = c.posA[j], b0 = c.posB[j], a1 = c.posA[j + 1], b1 = c.posB[j + 1];
-                AT_SWAP(a0, b0);
-                AT_SWAP(a1, b1);
+                const int d0 = AT_SWAP_D(a0, b0), d1 = AT_SWAP_D(a1, b1);
+                AT_SWAP(a0, b0, d0, 0u);
+                AT_SWAP(a1, b1, d1, 0u);
             }
             for (; j < jend; ++j) {
                 const int4 a0 = c.posA[j], b0 = c.posB[j];
-                AT_SWAP(a0, b0);
+                const int d0 = AT_SWAP_D(a0, b0);
+                AT_SWAP(a0, b0, d0, 0u);
             }
-#undef AT_SWAP
         } else {
-            for (; j < jend; ++j) {
-                const int4 a = c.posA[j], b = c.posB[j];
-                const int dg = outb - b.x + (int)tc[xri + a.y] + (int)tc[a.x + yci]
-                             + (int)tc[a.z + mci] + (int)tc[mri + a.w];
-                // the lane's mission directly before the partner: delta from prep
-                const int d = (j == i + 1 && ri == r) ? adjb : dg;
-                const bool tb = t1 | ((int)tabu_ri[b.z & 0xFFFF] > th);
-                const bool ok = j > i;
-                if (PACK5) {
-                    const bool bl = tb & !(d < thrb);
-                    const uint32_t p = (bl ? 0x80000000u : 0u) | ((uint32_t)d << 5) | ((uint32_t)b.w & 31u);
-                    mF = ok ? min(mF, p) : mF;
-                } else {
-                    const uint32_t p = ((uint32_t)d << 6) | ((uint32_t)b.w & 63u);
-                    mT = (ok && tb) ? min(mT, p) : mT;
-                    mF = (ok && !tb) ? min(mF, p) : mF;
-                }
+            // partners at or before the lane are masked; the lane's mission directly
+            // before the partner in one route takes its delta from prep
+#define AT_SWAP_DIAG(a, b, jj)                                                                 \
+    do {                                                                                       \
+        const int dg_ = AT_SWAP_D(a, b);                                                       \
+        const int d_ = ((jj) == i + 1 && ri == r) ? adjb : dg_;                                \
+        AT_SWAP(a, b, d_, (jj) > i ? 0u : 0xFFFFFFFFu);                                        \
+    } while (0)
+            for (; j + 2 <= jend; j += 2) {
+                const int4 a0 = c.posA[j], b0 = c.posB[j], a1 = c.posA[j + 1], b1 = c.posB[j + 1];
+                AT_SWAP_DIAG(a0, b0, j);
+                AT_SWAP_DIAG(a1, b1, j + 1);
             }
+            for (; j < jend; ++j) {
+                const int4 a0 = c.posA[j], b0 = c.posB[j];
+                AT_SWAP_DIAG(a0, b0, j);
+            }
+#undef AT_SWAP_DIAG
         }
-        if (act) {
-            if (PACK5) {
-                if (mF != 0xFFFFFFFFu) {
-                    const int d = (int)((mF >> 5) & 0x3FFFFFFu) - kPackBias;
-                    const int jw = j0 + c.prank[j0 + (int)(mF & 31u)];
-                    const uint32_t mj = c.seq[jw];
-                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                    best = umin64(best, pack_key((mF >> 31) != 0, d, swap_index(c.R, M, a, bm)));
-                }
-            } else {
-                if (mF != 0xFFFFFFFFu) {
-                    const int d = (int)(mF >> 6) - kPackBias;
-                    const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
-                    const uint32_t mj = c.seq[jw];
-                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                    best = umin64(best, pack_key(false, d, swap_index(c.R, M, a, bm)));
-                }
-                if (mT != 0xFFFFFFFFu) {
-                    const int d = (int)(mT >> 6) - kPackBias;
-                    const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
-                    const uint32_t mj = c.seq[jw];
-                    const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                    best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
-                }
+#undef AT_SWAP_D
+#undef AT_SWAP
+    }
+    uint64_t best = kKeyNone;
+    if (act) {
+        if (PACK5) {
+            if (mF != 0xFFFFFFFFu) {
+                const int d = (int)((mF >> 5) & 0x3FFFFFFu) - kPackBias;
+                const int jw = j0 + c.prank[j0 + (int)(mF & 31u)];
+                const uint32_t mj = c.seq[jw];
+                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                best = pack_key((mF >> 31) != 0, d, swap_index(c.R, M, a, bm));
+            }
+        } else {
+            if (mF != 0xFFFFFFFFu) {
+                const int d = (int)(mF >> 6) - kPackBias;
+                const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
+                const uint32_t mj = c.seq[jw];
+                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                best = pack_key(false, d, swap_index(c.R, M, a, bm));
+            }
+            if (mT != 0xFFFFFFFFu) {
+                const int d = (int)(mT >> 6) - kPackBias;
+                const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
+                const uint32_t mj = c.seq[jw];
+                const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
+                best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
             }
         }
     }
