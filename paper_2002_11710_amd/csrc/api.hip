@@ -102,6 +102,7 @@ int ring_slots(const at_params &pr)
 bool may_need_global(const at_instance &in, const at_params &pr)
 {
     if (pr.schedule == AT_SCHED_GLOBAL) return true;
+    if (in.n_missions >= (1 << 15) || in.n_missions + in.n_vehicles >= (1 << 16)) return true;   // move keys
     const int64_t B = compact_bound(in.n_locs, in.n_missions, in.n_vehicles);
     const uint32_t worst = lds_layout(in.n_missions, in.n_vehicles, (int)B, compact_stride((int)B, 4), 4,
                                       tabu_bytes(pr)).total;
@@ -315,6 +316,8 @@ static int plan_wave(JobHost &h, const InstDev &d)
     h.wtile = !constrained(d) && h.pr.form == AT_FORM_BEST;
     if (h.wtile) {
         // the unconstrained best form: the one-workgroup schedule's code on one wavefront
+        if (d.M >= (1 << 15) || d.M + d.V >= (1 << 16))
+            return fail(AT_ENOMEM, "instance too large for the wave schedule (%d missions, %d vehicles)", d.M, d.V);
         h.tb16 = tabu_bytes(h.pr) == 2 ? 1 : 0;
         h.esz16 = d.esz == 2 ? 1 : 0;
         h.lds = lds_layout(d.M, d.V, d.R, d.Cs, d.esz, h.tb16 ? 2 : 4).total;
@@ -352,7 +355,10 @@ int plan_job(JobHost &h, const InstDev &d, bool alone)
     // relocate column (measured on gfx950: 5% more batch throughput than equal widths)
     h.rchunk = std::min(64, 2 * h.chunk);
     h.groups = 1;
-    if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit) {
+    // the LDS-resident schedules pack a move as mission << 16 | gap (M < 2^15,
+    // M + V < 2^16); LDS itself runs out long before
+    const bool lds_keys = d.M < (1 << 15) && d.M + d.V < (1 << 16);
+    if (h.pr.schedule == AT_SCHED_GLOBAL || h.lds > kLdsLimit || !lds_keys) {
         if (!h.gstate) return fail(AT_ENOMEM, "solve needs the HBM-resident schedule but no state was reserved");
         h.kind = AT_SCHED_GLOBAL;
         // a requested block size above the schedule's limit applies to the other schedules only

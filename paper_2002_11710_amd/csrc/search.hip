@@ -150,6 +150,23 @@ __device__ __forceinline__ uint32_t swap_index(uint32_t R, uint32_t M, uint32_t 
     return R + a * M - (a * (a + 1u)) / 2u + (b - a - 1u);
 }
 
+// Move index inside the LDS-resident schedules' keys: relocate of mission m to
+// gap G as m << 16 | G, swap of missions a < b as 2^31 | a << 16 | b.  It orders
+// the moves as the slot index does (every relocate before every swap, each kind
+// by its pair), so the minimum key names the same move, and the decode on the
+// iteration's critical path is shifts instead of a division or a square root.
+// Needs M < 2^15 and M + V < 2^16 (the planner keeps larger solves on the
+// HBM-resident schedule).  The trace and the key dump take the slot index.
+__device__ __forceinline__ uint32_t lidx_swap(uint32_t a, uint32_t b)
+{
+    return 0x80000000u | (a << 16) | b;
+}
+
+__device__ __forceinline__ uint32_t lidx_slot(uint32_t ix, uint32_t R, uint32_t M, uint32_t NG)
+{
+    return (ix >> 31) ? swap_index(R, M, (ix >> 16) & 0x7FFFu, ix & 0xFFFFu) : (ix >> 16) * NG + (ix & 0xFFFFu);
+}
+
 __device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t k)
 {
     uint64_t z = seed + k * kGamma;
@@ -295,7 +312,7 @@ __device__ __forceinline__ uint64_t relocate_unit_flat(const Ctx &c, const TE *t
     if (!act || pm == 0xFFFFFFFFu) return kKeyNone;
     const int d = (int)((pm >> 6) & 0x1FFFFFFu) - kFlatBias;
     const uint32_t Gw = (uint32_t)G0 + (pm & 63u);
-    return pack_key((pm >> 31) != 0, d, (uint32_t)m * (uint32_t)c.NG + Gw);
+    return pack_key((pm >> 31) != 0, d, ((uint32_t)m << 16) | Gw);
 }
 
 template <typename TE, typename TB>
@@ -311,7 +328,7 @@ __device__ __forceinline__ uint64_t relocate_unit(const Ctx &c, const TE *tc, co
     const int mr = pa.x, mc = pa.y;
     const int remb = pb.y - pb.x + kPackBias;
     const int Gi = ii + ri;
-    const uint32_t ibase = (uint32_t)m * (uint32_t)c.NG;
+    const uint32_t ibase = (uint32_t)m << 16;
     // the unit's gap records (at most 64 columns), one per lane, read once and
     // handed to the column loop with readlane: one coalesced LDS read per unit
     // instead of a 16-byte broadcast per column
@@ -466,7 +483,7 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
                 const int jw = j0 + c.prank[j0 + (int)(mF & 31u)];
                 const uint32_t mj = c.seq[jw];
                 const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                best = pack_key((mF >> 31) != 0, d, swap_index(c.R, M, a, bm));
+                best = pack_key((mF >> 31) != 0, d, lidx_swap(a, bm));
             }
         } else {
             if (mF != 0xFFFFFFFFu) {
@@ -474,14 +491,14 @@ __device__ __forceinline__ uint64_t swap_unit(const Ctx &c, const TE *tc, const 
                 const int jw = j0 + c.prank[j0 + (int)(mF & 63u)];
                 const uint32_t mj = c.seq[jw];
                 const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                best = pack_key(false, d, swap_index(c.R, M, a, bm));
+                best = pack_key(false, d, lidx_swap(a, bm));
             }
             if (mT != 0xFFFFFFFFu) {
                 const int d = (int)(mT >> 6) - kPackBias;
                 const int jw = j0 + c.prank[j0 + (int)(mT & 63u)];
                 const uint32_t mj = c.seq[jw];
                 const uint32_t a = min((uint32_t)mi, mj), bm = max((uint32_t)mi, mj);
-                best = umin64(best, pack_key(!(d < thr), d, swap_index(c.R, M, a, bm)));
+                best = umin64(best, pack_key(!(d < thr), d, lidx_swap(a, bm)));
             }
         }
     }
@@ -1076,9 +1093,9 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 const int tval = t + J.tenure + 1;
                 GMove mv{};
                 bool wt = false;
-                if (ix < c.R) {
-                    const int m = (int)(ix / (uint32_t)c.NG);
-                    const int G = (int)(ix - (uint32_t)m * (uint32_t)c.NG);
+                if (!(ix >> 31)) {
+                    const int m = (int)(ix >> 16);
+                    const int G = (int)(ix & 0xFFFFu);
                     const int v = c.gap[G].w & 0xFFFF;
                     const int s = c.pof[m];
                     const int rs = c.rof[m];          // loads alongside pof[m]
@@ -1092,8 +1109,7 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                         if (lane == 0) tabu[rs * M + m] = (TB)tval;
                     }
                 } else {
-                    int m1, m2;
-                    swap_pair(ix - c.R, M, m1, m2);
+                    const int m1 = (int)((ix >> 16) & 0x7FFFu), m2 = (int)(ix & 0xFFFFu);
                     const int s1 = c.pof[m1], s2 = c.pof[m2];
                     const int r1 = c.rof[m1], r2 = c.rof[m2];
                     mv.kind = 2;
@@ -1130,10 +1146,10 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
         const uint32_t idx = (uint32_t)key;
         if (!use_tabu && d >= 0) { stopped = 1; break; }
         const bool was_tabu = c.red[66] != 0;
-        const bool is_swap = idx >= c.R;
+        const bool is_swap = (idx >> 31) != 0;
         cur += d;
         if (writer && tid == 0 && J.trace) {
-            J.tr_move[t] = idx;
+            J.tr_move[t] = lidx_slot(idx, c.R, (uint32_t)M, (uint32_t)c.NG);
             J.tr_delta[t] = d;
             J.tr_obj[t] = cur;
             J.tr_flags[t] = (uint8_t)((is_swap ? 1 : 0) | ((was_tabu && !blocked) ? 2 : 0) | (blocked ? 4 : 0));
@@ -2023,6 +2039,7 @@ __global__ void __launch_bounds__(1024) k_debug_keys(const JobDev *jp, const int
     if (tid < kWave) {
         uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
         w = wave_min(w);
+        if (w != kKeyNone) w = (w & 0xFFFFFFFF00000000ull) | lidx_slot((uint32_t)w, c.R, (uint32_t)M, (uint32_t)c.NG);
         if (lane == 0) keys[n_slots(M, V)] = w;
     }
 }
