@@ -192,20 +192,42 @@ __device__ __forceinline__ int route_of_pos(const int32_t *off, int V, int k)
 template <typename TE>
 __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nthr)
 {
-    const int CH = c.chunk;
-    for (int i = tid; i < c.M; i += nthr) {
+    const int CH = c.chunk, M = c.M;
+    for (int i = tid; i < M; i += nthr) {
+        // three rounds of LDS reads, each independent of the others in its round:
+        // positions (the neighbours' entries at clamped indices; a position opens
+        // its route when the one before it is in another route, and closes it when
+        // the one after it is), then missions and vehicles, then travel entries
+        const int im = max(i - 1, 0), ip = min(i + 1, M - 1), ip2 = min(i + 2, M - 1);
         const int m = c.seq[i], r = c.rt[i];
-        const int x = (i == c.off[r]) ? c.vrow[r] : c.mrow[c.seq[i - 1]];
-        const bool last = i + 1 == c.off[r + 1];
-        const int y = last ? c.vcol[r] : c.mcol[c.seq[i + 1]];
-        const int mc = c.mcol[m], mr = c.mrow[m];
-        const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
+        const int mp = c.seq[im], mn = c.seq[ip], mn2 = c.seq[ip2];
+        const int rp = c.rt[im], rn = c.rt[ip], rn2 = c.rt[ip2];
         // rank of m among the missions of this position's chunk: the chunk's entries
         // read 8 at a time (chunks start at multiples of 8 entries, 16-byte aligned;
-        // entries at or past M are masked)
-        const int base = i & ~(CH - 1), end = min(c.M, base + CH);   // CH: a power of two
+        // the array is padded to whole chunks and entries at or past M are masked)
+        const int base = i & ~(CH - 1), end = min(M, base + CH);   // CH: a power of two, >= 8
+        const uint4 q0 = *(const uint4 *)(c.seq + base);
+        const bool first = i == 0 || rp != r;
+        const bool last = i + 1 == M || rn != r;
+        const bool last2 = i + 2 >= M || rn2 != r;   // for !last: position i + 1 closes the route
+        const int vr = c.vrow[r], vc = c.vcol[r], endr = c.off[r + 1];
+        const int mc = c.mcol[m], mr = c.mrow[m];
+        const int xp = c.mrow[mp], yn = c.mcol[mn], mrn = c.mrow[mn], yn2 = c.mcol[mn2];
+        const int x = first ? vr : xp;
+        const int y = last ? vc : yn;
+        const int y2 = last2 ? vc : yn2;
+        const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
+        const int s1 = tc[mrn + mc], s2 = tc[mr + y2], s3 = tc[mrn + y2];
         int rank = 0;
-        for (int w = base; w < end; w += 8) {
+        {
+            const uint32_t e[4] = {q0.x, q0.y, q0.z, q0.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                rank += (base + 2 * h < end && (int)(e[h] & 0xFFFFu) < m) ? 1 : 0;
+                rank += (base + 2 * h + 1 < end && (int)(e[h] >> 16) < m) ? 1 : 0;
+            }
+        }
+        for (int w = base + 8; w < end; w += 8) {
             const uint4 q = *(const uint4 *)(c.seq + w);
             const uint32_t e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -215,27 +237,27 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
             }
         }
         // swapping m with its successor in the same route: P m n N -> P n m N
-        int adj = 0;
-        if (!last) {
-            const int n = c.seq[i + 1];
-            const int y2 = (i + 2 == c.off[r + 1]) ? c.vcol[r] : c.mcol[c.seq[i + 2]];
-            const int mrn = c.mrow[n];
-            adj = l + (int)tc[mrn + mc] + (int)tc[mr + y2] - a - bb - (int)tc[mrn + y2];
-        }
+        const int adj = last ? 0 : l + s1 + s2 - a - bb - s3;
         c.prank[base + rank] = (uint8_t)(i - base);
         c.posA[i] = make_int4(mr, mc, x, y);
         c.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
                               (int)((uint32_t)rank | ((uint32_t)(adj + kPackBias) << 6)));
         c.gap[i + r] = make_int4(x, mc, a, r);
-        c.gend[i + r] = (uint16_t)(c.off[r + 1] + r + 1);
+        c.gend[i + r] = (uint16_t)(endr + r + 1);
+        if (last) {
+            // the gap after the route's last mission: from m's exit row to the base
+            c.gap[i + 1 + r] = make_int4(mr, vc, bb, r);
+            c.gend[i + 1 + r] = (uint16_t)(endr + r + 1);
+        }
     }
-    // the gaps after each route's last mission: on the highest threads, which have
-    // no position of their own when M < nthr, so no thread runs two record chains
+    // the only gap of each empty route: on the highest threads, which have no
+    // position of their own when M < nthr
     for (int r = nthr - 1 - tid; r < c.V; r += nthr) {
-        const int e = c.off[r + 1];
-        const int x = (c.off[r] == e) ? c.vrow[r] : c.mrow[c.seq[e - 1]];
-        c.gap[e + r] = make_int4(x, c.vcol[r], (int)tc[x + c.vcol[r]], r);
-        c.gend[e + r] = (uint16_t)(e + r + 1);
+        const int e = c.off[r + 1], o = c.off[r], x = c.vrow[r], y = c.vcol[r];
+        if (o == e) {
+            c.gap[e + r] = make_int4(x, y, (int)tc[x + y], r);
+            c.gend[e + r] = (uint16_t)(e + r + 1);
+        }
     }
 }
 
