@@ -118,8 +118,9 @@ typedef struct at_params {
     int32_t n_groups;       /* workgroups per solve for MULTI/GLOBAL (0 = auto) */
     int32_t block;          /* threads per workgroup: 0 = auto, else 256, 512 or 1024 (the
                                HBM-resident schedule uses at most 512) */
-    int32_t chunk;          /* partner positions per swap work unit: 0 = auto, else 8, 16,
-                               32 or 64 (relocate units take twice as many gaps, at most 64) */
+    int32_t chunk;          /* partner positions per swap work unit: 0 = auto, else 4, 8,
+                               16, 32 or 64 (relocate units take twice as many gaps, at most
+                               64) */
     int32_t form;           /* AT_FORM_BEST or AT_FORM_SWEEP */
 } at_params;
 

@@ -63,8 +63,8 @@ int check_scalars(const at_instance *in, const at_params *pr)
     if ((int64_t)pr->max_iters + pr->tenure + 1 > INT32_MAX) return fail(AT_EINVAL, "max_iters + tenure too large");
     if (pr->block != 0 && pr->block != 256 && pr->block != 512 && pr->block != 1024)
         return fail(AT_EINVAL, "block must be 0, 256, 512 or 1024");
-    if (pr->chunk != 0 && (pr->chunk != 8 && pr->chunk != 16 && pr->chunk != 32 && pr->chunk != 64))
-        return fail(AT_EINVAL, "chunk must be 0, 8, 16, 32 or 64");
+    if (pr->chunk != 0 && pr->chunk != 4 && pr->chunk != 8 && pr->chunk != 16 && pr->chunk != 32 && pr->chunk != 64)
+        return fail(AT_EINVAL, "chunk must be 0, 4, 8, 16, 32 or 64");
     if (pr->schedule < AT_SCHED_AUTO || pr->schedule > AT_SCHED_WAVE) return fail(AT_EINVAL, "bad schedule");
     if (pr->n_groups < 0 || pr->n_groups > 4096) return fail(AT_EINVAL, "n_groups outside [0, 4096]");
     if (pr->form != AT_FORM_BEST && pr->form != AT_FORM_SWEEP) return fail(AT_EINVAL, "bad form %d", pr->form);
@@ -402,18 +402,27 @@ bool multi_eligible(const JobHost &h)
 // for the wavefront with the most work), up to 96 workgroups (more slots to poll
 // cost more than the eval saves).  One solve alone: workgroups [0, groups),
 // slot set 0.
-int plan_multi(JobHost &h, const InstDev &d)
+int plan_multi(JobHost &h, const InstDev &d, bool small_units)
 {
     if (!h.pr.block) h.block = 512;
-    if (!h.pr.chunk) h.chunk = 8;
-    h.rchunk = std::min(64, 2 * h.chunk);
     const int cap = max_groups_multi(h.block, h.lds, h.tb16, h.esz16);
-    int64_t units = 0;
-    for (int64_t jb = 0; jb < d.M; jb += kWave)
-        units += (d.M + d.V + h.rchunk - 1) / h.rchunk + (d.M - jb + h.chunk - 1) / h.chunk;
     const int64_t waves = std::max(1, h.block / kWave);
+    auto units_of = [&](int ch) {
+        const int rch = std::min(64, 2 * ch);
+        int64_t u = 0;
+        for (int64_t jb = 0; jb < d.M; jb += kWave)
+            u += (d.M + d.V + rch - 1) / rch + (d.M - jb + ch - 1) / ch;
+        return u;
+    };
+    // the iteration waits for the slowest unit: half-width units (4 partners, 8
+    // gaps) while they still leave every wavefront at most one unit at the group
+    // limit, else 8-partner units
+    if (!h.pr.chunk)
+        h.chunk = (small_units && units_of(4) <= (int64_t)kMultiMaxGroups * waves) ? 4 : 8;
+    h.rchunk = std::min(64, 2 * h.chunk);
+    const int64_t units = units_of(h.chunk);
     int g = h.pr.n_groups ? h.pr.n_groups
-                          : (int)std::max<int64_t>(1, std::min<int64_t>(96, (units + waves - 1) / waves));
+                          : (int)std::max<int64_t>(1, std::min<int64_t>(kMultiMaxGroups, (units + waves - 1) / waves));
     g = std::min(g, std::min(std::min(cap, num_cus()), kMaxGroups));
     if (g < 1) return fail(AT_EDEVICE, "cannot co-schedule the multi-workgroup search");
     h.kind = AT_SCHED_MULTI;
@@ -437,17 +446,25 @@ int plan_multi_batch(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih)
     if (n < 2 || n > kMaxMultiJobs) return AT_OK;
     for (const JobHost &h : jobs)
         if (!multi_eligible(h) || h.tb16 != jobs[0].tb16 || h.esz16 != jobs[0].esz16) return AT_OK;
-    std::vector<JobHost> m = jobs;
+    std::vector<JobHost> m;
     uint32_t lds = 0;
     int64_t want = 0;
-    for (JobHost &h : m) {
-        int rc = plan_multi(h, ih[(size_t)h.inst]);
-        if (rc) return rc;
-        if (h.block != m[0].block) return AT_OK;
-        lds = std::max(lds, h.lds);
-        want += h.groups;
+    int cap = 0;
+    // half-width units only while every solve keeps the groups it asks for
+    for (const bool small_units : {true, false}) {
+        m = jobs;
+        lds = 0;
+        want = 0;
+        for (JobHost &h : m) {
+            int rc = plan_multi(h, ih[(size_t)h.inst], small_units);
+            if (rc) return rc;
+            if (h.block != m[0].block) return AT_OK;
+            lds = std::max(lds, h.lds);
+            want += h.groups;
+        }
+        cap = max_groups_multi(m[0].block, lds, m[0].tb16, m[0].esz16);
+        if (want <= cap) break;
     }
-    const int cap = max_groups_multi(m[0].block, lds, m[0].tb16, m[0].esz16);
     if (cap < n) return AT_OK;
     if (want > cap) {
         // scale to the co-resident limit; the floor of 1 can overshoot it by a few groups,

@@ -56,8 +56,9 @@ int plan_job(JobHost &h, const InstDev &d, bool alone);
 // Solves at or above this many move slots take the multi-workgroup schedule
 // under AUTO when they are alone in their call (or in a small batch).
 constexpr int64_t kMultiMinSlots = 20000;
+constexpr int kMultiMaxGroups = 96;       // workgroups of one multi-workgroup solve (auto plan)
 bool multi_eligible(const JobHost &h);
-int plan_multi(JobHost &h, const InstDev &d);
+int plan_multi(JobHost &h, const InstDev &d, bool small_units = true);
 int plan_multi_batch(std::vector<JobHost> &jobs, const std::vector<InstDev> &ih);
 int fill_job(JobDev &j, const JobHost &h, const InstDev *dev_inst, JobScal *scal);
 int upload_gstates(const std::vector<JobHost> &jobs, const std::vector<InstDev> &ih, hipStream_t s);

@@ -202,11 +202,13 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const int m = c.seq[i], r = c.rt[i];
         const int mp = c.seq[im], mn = c.seq[ip], mn2 = c.seq[ip2];
         const int rp = c.rt[im], rn = c.rt[ip], rn2 = c.rt[ip2];
-        // rank of m among the missions of this position's chunk: the chunk's entries
-        // read 8 at a time (chunks start at multiples of 8 entries, 16-byte aligned;
-        // the array is padded to whole chunks and entries at or past M are masked)
-        const int base = i & ~(CH - 1), end = min(M, base + CH);   // CH: a power of two, >= 8
-        const uint4 q0 = *(const uint4 *)(c.seq + base);
+        // rank of m among the missions of this position's chunk: the entries read 8
+        // at a time from the 8-entry boundary at or below the chunk's start (16-byte
+        // aligned; the array is padded to whole 8-entry groups), counting only those
+        // in the chunk (a 4-entry chunk is half of one group)
+        const int base = i & ~(CH - 1), end = min(M, base + CH);   // CH: a power of two, >= 4
+        const int w0 = base & ~7;
+        const uint4 q0 = *(const uint4 *)(c.seq + w0);
         const bool first = i == 0 || rp != r;
         const bool last = i + 1 == M || rn != r;
         const bool last2 = i + 2 >= M || rn2 != r;   // for !last: position i + 1 closes the route
@@ -219,7 +221,16 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const int a = tc[x + mc], bb = tc[mr + y], l = tc[x + y];
         const int s1 = tc[mrn + mc], s2 = tc[mr + y2], s3 = tc[mrn + y2];
         int rank = 0;
-        {
+        if (CH == 4) {
+            // the chunk is the group's low or high half
+            const bool hi = base != w0;
+            const uint32_t e[2] = {hi ? q0.z : q0.x, hi ? q0.w : q0.y};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                rank += (base + 2 * h < end && (int)(e[h] & 0xFFFFu) < m) ? 1 : 0;
+                rank += (base + 2 * h + 1 < end && (int)(e[h] >> 16) < m) ? 1 : 0;
+            }
+        } else {
             const uint32_t e[4] = {q0.x, q0.y, q0.z, q0.w};
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
@@ -227,7 +238,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
                 rank += (base + 2 * h + 1 < end && (int)(e[h] >> 16) < m) ? 1 : 0;
             }
         }
-        for (int w = base + 8; w < end; w += 8) {
+        for (int w = w0 + 8; w < end; w += 8) {
             const uint4 q = *(const uint4 *)(c.seq + w);
             const uint32_t e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -1085,24 +1096,30 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 if (lane == 0)
                     __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+                // up to four slots per lane (kMaxGroups = 4 x 64), all polled together
+                static_assert(kMaxGroups <= 4 * kWave, "four slots per lane");
                 uint64_t bestk = kKeyNone;
                 uint32_t ab = 0;
-                for (int base = 0; base < nwg && !ab; base += kWave) {
-                    const int w2 = base + lane;
-                    bool ready = w2 >= nwg;
-                    uint64_t v = 0;
-                    uint32_t spins = 0;
-                    for (;;) {
-                        if (!ready) {
-                            v = __hip_atomic_load(&slots[w2 * kSlotStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ready = (v >> 63) == tag;
+                uint64_t v[4] = {0, 0, 0, 0};
+                bool ready[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ready[q] = q * kWave + lane >= nwg;
+                uint32_t spins = 0;
+                for (;;) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (!ready[q]) {
+                            v[q] = __hip_atomic_load(&slots[(q * kWave + lane) * kSlotStride], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                            ready[q] = (v[q] >> 63) == tag;
                         }
-                        if (__all(ready)) break;
-                        if (++spins > kSpinLimit) { ab = 1; break; }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    if (w2 < nwg && ready) bestk = umin64(bestk, decode_slot(v));
+                    if (__all(ready[0] && ready[1] && ready[2] && ready[3])) break;
+                    if (++spins > kSpinLimit) { ab = 1; break; }
+                    __builtin_amdgcn_s_sleep(1);
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q * kWave + lane < nwg && ready[q]) bestk = umin64(bestk, decode_slot(v[q]));
                 w = wave_min(bestk);
                 xab = ab;
                 if (lane == 0) c.red[65] = ab;

@@ -51,7 +51,7 @@ def _random_state(P, rng, tenure_span=6):
 
 @pytest.mark.parametrize("shape", [(20, 2, 1, 1), (20, 2, 1, 2), (20, 3, 3, 12), (30, 2, 5, 70),
                                    (60, 4, 7, 130), (120, 10, 16, 400)])
-@pytest.mark.parametrize("chunk", [8, 32])
+@pytest.mark.parametrize("chunk", [4, 8, 32])
 def test_every_slot_key(shape, chunk):
     F, B, V, M = shape
     inst = make_instance(7 + M, F, B, V, M)
@@ -72,7 +72,7 @@ def test_every_slot_key(shape, chunk):
                 assert fast == int(want.min()), (shape, k, t, best - cur, hex(fast), hex(int(want.min())))
 
 
-@pytest.mark.parametrize("chunk", [8, 32])
+@pytest.mark.parametrize("chunk", [4, 8, 32])
 def test_every_slot_key_wide_entries(chunk):
     """Travel times above 65535 s (5 km/h): the compact block holds 32-bit
     entries, and every slot's key and the minimum still equal the oracle's."""
@@ -295,7 +295,7 @@ def test_determinism_repeated():
     dev = _dev(inst)
     first = at.solve(dev, tenure=9, iters=400)
     tm = first["tr_move"].cpu().numpy()
-    for block, chunk in ((256, 8), (512, 16), (1024, 64)):
+    for block, chunk in ((256, 8), (512, 16), (1024, 64), (512, 4)):
         g = at.solve(dev, tenure=9, iters=400, block=block, chunk=chunk, schedule=1)
         assert np.array_equal(g["tr_move"].cpu().numpy(), tm), (block, chunk)
     for groups in (2, 5):
