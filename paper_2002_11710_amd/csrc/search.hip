@@ -982,6 +982,12 @@ __device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int la
         constexpr int U = 8;
         const int lo = mv.lo, hi = mv.hi, q = mv.q, n = hi - lo + 1;
         const bool up = mv.dir > 0;
+        // the offsets of the routes after the left one, up to the right one, move by
+        // one: the first 64 are read here, beside the shifted entries, and written
+        // with them
+        const int rlo = min(mv.v, mv.rs) + 1, rhi = max(mv.v, mv.rs), dlt = mv.v > mv.rs ? -1 : 1;
+        const int r0 = rlo + lane;
+        const int o0 = r0 <= rhi ? c.off[r0] : 0;
         for (int c0 = 0; c0 < n; c0 += U * kWave) {
             int val[U];
 #pragma unroll
@@ -1009,8 +1015,8 @@ __device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int la
             }
             __asm__ volatile("" ::: "memory");
         }
-        if (mv.v > mv.rs) for (int r = mv.rs + 1 + lane; r <= mv.v; r += kWave) c.off[r] -= 1;
-        if (mv.v < mv.rs) for (int r = mv.v + 1 + lane; r <= mv.rs; r += kWave) c.off[r] += 1;
+        if (r0 <= rhi) c.off[r0] = o0 + dlt;
+        for (int r = r0 + kWave; r <= rhi; r += kWave) c.off[r] += dlt;
     } else if (mv.kind == 2 && lane == 0) {
         c.seq[mv.s1] = (uint16_t)mv.m2;
         c.seq[mv.s2] = (uint16_t)mv.m1;
@@ -1068,9 +1074,11 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
     const UnitStart us0 = unit_start(c, gw);
     int t = J.t_begin;
     bool aborted = false;
-    for (; t < J.t_end && !stopped; ++t) {
+    if (t < J.t_end && !stopped) {
         prep<TE>(c, tc, tid, nthr);
         bsync<WAVE>();
+    }
+    for (; t < J.t_end && !stopped; ++t) {
         int thr = INT32_MIN;
         if (J.aspiration) {
             const int64_t g = best - cur;
@@ -1080,6 +1088,8 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
         k = wave_min(k);
         if (lane == 0) c.red[wave] = k;
         bsync<WAVE>();
+        GMove mv{};
+        bool moved = false;   // wave 0: a move was decoded
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
             w = wave_min(w);
@@ -1126,12 +1136,9 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
             }
             if (lane == 0) c.red[64] = w;
             if (!xab && w != kKeyNone) {
-                // decode the move (uniform over the wave), publish it to the workgroup
-                // and record the tabu entries it sets (every wave is past the eval)
+                // decode the move (uniform over the wave) and apply it
                 const uint32_t ix = (uint32_t)w;
-                const int tval = t + J.tenure + 1;
-                GMove mv{};
-                bool wt = false;
+                moved = true;
                 if (!(ix >> 31)) {
                     const int m = (int)(ix >> 16);
                     const int G = (int)(ix & 0xFFFFu);
@@ -1143,10 +1150,6 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                     mv.kind = 1;
                     mv.m = m; mv.v = v; mv.q = q; mv.rs = rs;
                     mv.lo = min(s, q); mv.hi = max(s, q); mv.dir = q >= s ? 1 : -1;
-                    if (use_tabu) {
-                        wt = (int)tabu[v * M + m] > t;
-                        if (lane == 0) tabu[rs * M + m] = (TB)tval;
-                    }
                 } else {
                     const int m1 = (int)((ix >> 16) & 0x7FFFu), m2 = (int)(ix & 0xFFFFu);
                     const int s1 = c.pof[m1], s2 = c.pof[m2];
@@ -1154,15 +1157,7 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                     mv.kind = 2;
                     mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
                     mv.v = r1; mv.rs = r2;            // the two vehicles
-                    if (use_tabu) {
-                        wt = (int)tabu[r2 * M + m1] > t || (int)tabu[r1 * M + m2] > t;
-                        if (lane == 0) {
-                            tabu[r1 * M + m1] = (TB)tval;
-                            tabu[r2 * M + m2] = (TB)tval;
-                        }
-                    }
                 }
-                if (lane == 0) c.red[66] = wt ? 1 : 0;
                 // apply it before the barrier that publishes the key (the neighbourhood
                 // search stops without applying a move that does not improve)
                 const int dw = (int)((uint32_t)(w >> 32) & 0x7FFFFFFFu) - kDeltaBias;
@@ -1172,32 +1167,55 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
         bsync<WAVE>();   // the move is decoded and applied
         if (MULTI && c.red[65]) { aborted = true; break; }
         const uint64_t key = c.red[64];
+        uint32_t tr_idx = 0xFFFFFFFFu;   // this iteration's trace record (thread 0)
+        int tr_d = 0;
+        uint8_t tr_fl = 0;
         if (key == kKeyNone) {
             // no move exists (at most one mission on a single vehicle)
             if (!use_tabu) { stopped = 1; break; }
-            if (writer && tid == 0 && J.trace) {
-                J.tr_move[t] = 0xFFFFFFFFu; J.tr_delta[t] = 0; J.tr_obj[t] = cur; J.tr_flags[t] = 0;
+        } else {
+            const bool blocked = (key >> 63) != 0;
+            const int d = (int)((uint32_t)(key >> 32) & 0x7FFFFFFFu) - kDeltaBias;
+            const uint32_t idx = (uint32_t)key;
+            if (!use_tabu && d >= 0) { stopped = 1; break; }
+            cur += d;
+            tr_idx = idx;
+            tr_d = d;
+            tr_fl = (uint8_t)(((idx >> 31) ? 1 : 0) | (blocked ? 4 : 0));
+            if (cur < best) {
+                best = cur;
+                best_iter = t;
+                if (writer) snapshot(c, J, tid, nthr);
             }
-            continue;
         }
-        const bool blocked = (key >> 63) != 0;
-        const int d = (int)((uint32_t)(key >> 32) & 0x7FFFFFFFu) - kDeltaBias;
-        const uint32_t idx = (uint32_t)key;
-        if (!use_tabu && d >= 0) { stopped = 1; break; }
-        const bool was_tabu = c.red[66] != 0;
-        const bool is_swap = (idx >> 31) != 0;
-        cur += d;
-        if (writer && tid == 0 && J.trace) {
-            J.tr_move[t] = lidx_slot(idx, c.R, (uint32_t)M, (uint32_t)c.NG);
-            J.tr_delta[t] = d;
-            J.tr_obj[t] = cur;
-            J.tr_flags[t] = (uint8_t)((is_swap ? 1 : 0) | ((was_tabu && !blocked) ? 2 : 0) | (blocked ? 4 : 0));
+        // the next iteration's records (they depend on the routes only)
+        if (t + 1 < J.t_end) prep<TE>(c, tc, tid, nthr);
+        if (tid == 0) {
+            // thread 0 (lane 0 of the wave that decoded the move) reads whether the move
+            // was tabu and makes the moved missions tabu for the vehicles they leave,
+            // behind its share of the records: nothing reads the tabu table before the
+            // next eval, after the barrier below
+            bool was_tabu = false;
+            if (use_tabu && moved) {
+                const int tval = t + J.tenure + 1;
+                if (mv.kind == 1) {
+                    was_tabu = (int)tabu[mv.v * M + mv.m] > t;
+                    tabu[mv.rs * M + mv.m] = (TB)tval;
+                } else {
+                    was_tabu = (int)tabu[mv.rs * M + mv.m1] > t || (int)tabu[mv.v * M + mv.m2] > t;
+                    tabu[mv.v * M + mv.m1] = (TB)tval;
+                    tabu[mv.rs * M + mv.m2] = (TB)tval;
+                }
+            }
+            if (writer && J.trace) {
+                const bool blocked = (tr_fl & 4) != 0;
+                J.tr_move[t] = tr_idx == 0xFFFFFFFFu ? tr_idx : lidx_slot(tr_idx, c.R, (uint32_t)M, (uint32_t)c.NG);
+                J.tr_delta[t] = tr_d;
+                J.tr_obj[t] = cur;
+                J.tr_flags[t] = (uint8_t)(tr_fl | ((was_tabu && !blocked) ? 2 : 0));
+            }
         }
-        if (cur < best) {
-            best = cur;
-            best_iter = t;
-            if (writer) snapshot(c, J, tid, nthr);
-        }
+        bsync<WAVE>();   // the records and the tabu entries are written
     }
     if (!writer) return;
     if (J.fin_off && !aborted) write_routes(c, J.fin_off, J.fin_seq, nullptr, tid, nthr);
