@@ -105,7 +105,7 @@ def parse():
                     help="requests of the stream also solved one at_solve at a time (the plain form)")
     ap.add_argument("--serve-chunk", type=int, default=250,
                     help="iterations per serving launch, at least, of a solve that runs on its own workgroups")
-    ap.add_argument("--serve-slots", type=int, default=1024, help="concurrent solves in the server")
+    ap.add_argument("--serve-slots", type=int, default=2048, help="concurrent solves in the server")
     ap.add_argument("--stress", type=int, default=1000,
                     help="also run the 256 x 10000 stress instance for this many iterations "
                          "(Tabu and NS; 0: skip)")
