@@ -463,3 +463,28 @@ def test_batch_of_many_large_solves_keeps_one_workgroup_each():
         alone = at.solve(d, tenure=7, iters=25)
         assert np.array_equal(gpu_to_np(res[k])["tr_move"], gpu_to_np(alone)["tr_move"]), k
         assert res[k]["best_obj"] == alone["best_obj"], k
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 0), (2, 7)])
+def test_half_width_units_ragged(sched, groups):
+    """Units of 4 partners and 8 gaps (chunk 4) on a ragged size: 333 missions on
+    11 vehicles (a last tile of 13 lanes, chunks that end inside a tile), Tabu and
+    NS, on the one-workgroup and multi-workgroup schedules, equal to the oracle."""
+    inst = make_instance(555, 250, 6, 11, 333)
+    dev = _dev(inst)
+    for variant in (0, 1):
+        _, o = oracle_solve(inst, variant=variant, tenure=9, iters=300)
+        g = at.solve(dev, variant=variant, tenure=9, iters=300, schedule=sched, n_groups=groups, chunk=4)
+        assert_same_result(o, g, f"chunk 4 schedule {sched} groups {groups} variant {variant}")
+
+
+def test_batch_of_eight_large_solves_shares_one_multi_launch():
+    """Eight restarts of the 16 x 400 instance in one call: more half-width groups
+    than the GPU holds at once, so the shared multi-workgroup launch takes
+    8-partner units; every restart equals its oracle run."""
+    from gen.instances import restart_seed
+    inst = m400_instance(0)
+    res = at.solve_batch([_dev(inst)], [at._capi.make_params(at.AT_TABU, 15, 60, True, 5, True)], 8)
+    for r in range(8):
+        _, o = oracle_solve(inst, tenure=15, iters=60, restart_seed=restart_seed(5, r))
+        assert_same_result(o, res[r], f"eight-restart batch, restart {r}")
