@@ -1106,30 +1106,65 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 if (lane == 0)
                     __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                // up to four slots per lane (kMaxGroups = 4 x 64), all polled together
+                // NQ slots per lane (2 up to 128 workgroups, else 4: kMaxGroups = 4 x
+                // 64), two loads of each in flight: the older is checked while the
+                // newer travels, so a slot is seen about half a round trip sooner after
+                // it is written than with one load at a time.  Every lane loads every
+                // round (lanes past the last slot reread slot 0 and ignore it): no
+                // branch around a load, so only the older loads are waited for
                 static_assert(kMaxGroups <= 4 * kWave, "four slots per lane");
                 uint64_t bestk = kKeyNone;
                 uint32_t ab = 0;
-                uint64_t v[4] = {0, 0, 0, 0};
-                bool ready[4];
+                auto exchange = [&](auto nq) {
+                    constexpr int NQ = decltype(nq)::value;
+                    uint64_t v[NQ], va[NQ], vb[NQ];
+                    bool ready[NQ];
+                    const uint64_t *src[NQ];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) ready[q] = q * kWave + lane >= nwg;
-                uint32_t spins = 0;
-                for (;;) {
+                    for (int q = 0; q < NQ; ++q) {
+                        const int w = q * kWave + lane;
+                        ready[q] = w >= nwg;
+                        src[q] = &slots[(w < nwg ? w : 0) * kSlotStride];
+                        v[q] = 0;
+                    }
+                    auto reload = [&](uint64_t (&x)[NQ]) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (!ready[q]) {
-                            v[q] = __hip_atomic_load(&slots[(q * kWave + lane) * kSlotStride], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                            ready[q] = (v[q] >> 63) == tag;
+                        for (int q = 0; q < NQ; ++q)
+                            x[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    };
+                    auto check = [&](const uint64_t (&x)[NQ]) {
+                        bool all = true;
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            const bool now = !ready[q] && (x[q] >> 63) == tag;
+                            v[q] = now ? x[q] : v[q];
+                            ready[q] = ready[q] || now;
+                            all = all && ready[q];
                         }
-                    if (__all(ready[0] && ready[1] && ready[2] && ready[3])) break;
-                    if (++spins > kSpinLimit) { ab = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
+                        return __all(all);
+                    };
+                    reload(va);
+                    __builtin_amdgcn_s_sleep(4);
+                    reload(vb);
+                    uint32_t spins = 0;
+                    // unrolled by two, so that neither load is copied: check the older,
+                    // reload it, check the other
+                    for (;;) {
+                        if (check(va)) break;
+                        if (++spins > kSpinLimit) { ab = 1; break; }
+                        reload(va);
+                        if (check(vb)) break;
+                        if (++spins > kSpinLimit) { ab = 1; break; }
+                        reload(vb);
+                    }
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q * kWave + lane < nwg && ready[q]) bestk = umin64(bestk, decode_slot(v[q]));
+                    for (int q = 0; q < NQ; ++q)
+                        if (q * kWave + lane < nwg && ready[q]) bestk = umin64(bestk, decode_slot(v[q]));
+                };
+                if (nwg <= 2 * kWave)
+                    exchange(std::integral_constant<int, 2>{});
+                else
+                    exchange(std::integral_constant<int, 4>{});
                 w = wave_min(bestk);
                 xab = ab;
                 if (lane == 0) c.red[65] = ab;
