@@ -1027,6 +1027,75 @@ __device__ __forceinline__ void apply_wave(const Ctx &c, const GMove &mv, int la
     }
 }
 
+// Exchange polling of the multi-workgroup schedule (wave 0 of a workgroup, all
+// lanes active): the minimum of the keys in the nwg slots (one per 128-byte line)
+// once every slot carries `tag`, or kKeyNone with ab = 1 when give_up(spins) says
+// so.  NQ slots per lane (2 up to 128 workgroups, else 4: kMaxGroups = 4 x 64),
+// two loads of each in flight: the older is checked while the newer travels, so a
+// slot is seen about half a round trip sooner after it is written than with one
+// load at a time (a third load in flight measured slower).  Every lane loads every
+// round (lanes past the last slot reread slot 0 and ignore it): no branch around a
+// load, so only the older loads are waited for.
+template <typename GiveUp>
+__device__ __forceinline__ uint64_t poll_slots(const uint64_t *slots, int nwg, uint64_t tag, int lane,
+                                               uint32_t &ab, GiveUp give_up)
+{
+    static_assert(kMaxGroups <= 4 * kWave, "four slots per lane");
+    uint64_t bestk = kKeyNone;
+    ab = 0;
+    auto run = [&](auto nq) {
+        constexpr int NQ = decltype(nq)::value;
+        uint64_t v[NQ], va[NQ], vb[NQ];
+        bool ready[NQ];
+        const uint64_t *src[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int w = q * kWave + lane;
+            ready[q] = w >= nwg;
+            src[q] = &slots[(w < nwg ? w : 0) * kSlotStride];
+            v[q] = 0;
+        }
+        auto reload = [&](uint64_t (&x)[NQ]) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                x[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        auto check = [&](const uint64_t (&x)[NQ]) {
+            bool all = true;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const bool now = !ready[q] && (x[q] >> 63) == tag;
+                v[q] = now ? x[q] : v[q];
+                ready[q] = ready[q] || now;
+                all = all && ready[q];
+            }
+            return __all(all);
+        };
+        reload(va);
+        __builtin_amdgcn_s_sleep(4);
+        reload(vb);
+        uint32_t spins = 0;
+        // unrolled by two, so that neither load is copied: check the older, reload
+        // it, check the other
+        for (;;) {
+            if (check(va)) break;
+            if (give_up(++spins)) { ab = 1; break; }
+            reload(va);
+            if (check(vb)) break;
+            if (give_up(++spins)) { ab = 1; break; }
+            reload(vb);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q * kWave + lane < nwg && ready[q]) bestk = umin64(bestk, decode_slot(v[q]));
+    };
+    if (nwg <= 2 * kWave)
+        run(std::integral_constant<int, 2>{});
+    else
+        run(std::integral_constant<int, 4>{});
+    return bestk;
+}
+
 template <typename TE, typename TB, bool MULTI, bool WAVE = false>
 __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int nwg, Xchg *xs)
 {
@@ -1106,65 +1175,9 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 if (lane == 0)
                     __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(w, tag), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                // NQ slots per lane (2 up to 128 workgroups, else 4: kMaxGroups = 4 x
-                // 64), two loads of each in flight: the older is checked while the
-                // newer travels, so a slot is seen about half a round trip sooner after
-                // it is written than with one load at a time.  Every lane loads every
-                // round (lanes past the last slot reread slot 0 and ignore it): no
-                // branch around a load, so only the older loads are waited for
-                static_assert(kMaxGroups <= 4 * kWave, "four slots per lane");
-                uint64_t bestk = kKeyNone;
                 uint32_t ab = 0;
-                auto exchange = [&](auto nq) {
-                    constexpr int NQ = decltype(nq)::value;
-                    uint64_t v[NQ], va[NQ], vb[NQ];
-                    bool ready[NQ];
-                    const uint64_t *src[NQ];
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        const int w = q * kWave + lane;
-                        ready[q] = w >= nwg;
-                        src[q] = &slots[(w < nwg ? w : 0) * kSlotStride];
-                        v[q] = 0;
-                    }
-                    auto reload = [&](uint64_t (&x)[NQ]) {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            x[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    };
-                    auto check = [&](const uint64_t (&x)[NQ]) {
-                        bool all = true;
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q) {
-                            const bool now = !ready[q] && (x[q] >> 63) == tag;
-                            v[q] = now ? x[q] : v[q];
-                            ready[q] = ready[q] || now;
-                            all = all && ready[q];
-                        }
-                        return __all(all);
-                    };
-                    reload(va);
-                    __builtin_amdgcn_s_sleep(4);
-                    reload(vb);
-                    uint32_t spins = 0;
-                    // unrolled by two, so that neither load is copied: check the older,
-                    // reload it, check the other
-                    for (;;) {
-                        if (check(va)) break;
-                        if (++spins > kSpinLimit) { ab = 1; break; }
-                        reload(va);
-                        if (check(vb)) break;
-                        if (++spins > kSpinLimit) { ab = 1; break; }
-                        reload(vb);
-                    }
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (q * kWave + lane < nwg && ready[q]) bestk = umin64(bestk, decode_slot(v[q]));
-                };
-                if (nwg <= 2 * kWave)
-                    exchange(std::integral_constant<int, 2>{});
-                else
-                    exchange(std::integral_constant<int, 4>{});
+                const uint64_t bestk = poll_slots(slots, nwg, tag, lane, ab,
+                                                  [](uint32_t spins) { return spins > kSpinLimit; });
                 w = wave_min(bestk);
                 xab = ab;
                 if (lane == 0) c.red[65] = ab;
@@ -1308,6 +1321,8 @@ __device__ __forceinline__ bool group_exchange(GlobalBufs &B, int wg, int nwg, u
         if (lane == 0)
             __hip_atomic_store(&slots[wg * kSlotStride], encode_slot(key, tag), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
+        // one load per slot at a time: with up to 256 workgroups polling, a second
+        // load in flight per slot (as in the multi-workgroup exchange) measured slower
         const uint64_t t0 = wall_clock64();
         uint64_t best = kKeyNone;
         uint32_t ab = 0, spins = 0;
