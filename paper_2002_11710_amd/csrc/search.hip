@@ -9,26 +9,32 @@
 //           gets its cost delta; the move is blocked if it puts a mission into
 //           a vehicle it left within `tenure` iterations and does not beat the
 //           best objective (aspiration); the best move is the smallest 64-bit
-//              blocked << 63 | (delta + 2^30) << 32 | slot index
-//   apply   every thread decodes the winner; the flat route array is shifted in
-//           two LDS phases; the moved missions become tabu for the vehicles
-//           they left; the trace record and, on a new best, the routes are
-//           written out.
+//              blocked << 63 | (delta + 2^30) << 32 | move index
+//           (the slot index, or inside the LDS-resident schedules an
+//           order-preserving packing of it that decodes with shifts)
+//   apply   the winner is decoded (by wavefront 0 of each workgroup in the
+//           LDS-resident schedules, by every workgroup's threads in the
+//           HBM-resident one) and the flat route array shifted; the moved
+//           missions become tabu for the vehicles they left; the trace record
+//           and, on a new best, the routes are written out.
 //
 // Work layout of eval.  Lanes own 64 consecutive route positions (a tile), one
 // mission each, whose values stay in registers; a unit is a run of `chunk`
-// columns -- gaps (relocate) or partner positions (swap) -- read as LDS
-// broadcasts.  Units are dealt round-robin to every wavefront of the solve.
-// Within a unit the columns are cut at vehicle boundaries; inside a segment
+// partner positions (swap) or `2 chunk` gaps (relocate).  Units are dealt
+// round-robin to every wavefront of the solve.  In the one-workgroup schedule
+// a relocate unit's columns are cut at vehicle boundaries; inside a segment
 // the tabu status of a relocate depends only on (mission, vehicle), so each
 // lane keeps a 32-bit running minimum of (delta + 2^25) << 6 | column rank and
 // turns it into a 64-bit key once per segment (a blocked move can only win a
 // segment if every move of the segment with the same or smaller delta is
-// blocked too, since aspiration only depends on the delta).  Swaps keep two
-// such minima (tabu / not tabu) per segment.  Column ranks follow the slot
-// index order for a fixed lane: the gap offset for relocates, the partner's
-// mission id for swaps (ranked inside the chunk by prep), so ties resolve to
-// the smallest slot index exactly as the full 64-bit comparison would.
+// blocked too, since aspiration only depends on the delta); the
+// multi-workgroup schedule's relocate units fold a per-lane tabu mask into one
+// minimum over the unit.  Swap units keep one minimum of blocked << 31 |
+// (delta + 2^25) << 5 | rank over the whole unit (two, tabu and not tabu, for
+// 64-partner units).  Column ranks follow the slot index order for a fixed
+// lane: the gap offset for relocates, the partner's mission id for swaps
+// (ranked inside the chunk by prep), so ties resolve to the smallest slot
+// index exactly as the full 64-bit comparison would.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -1166,7 +1172,7 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
             if (MULTI) {
                 // Each workgroup publishes its minimum in its own slot, tagged with
                 // bit 1 of the iteration; wave 0 of every workgroup polls all slots
-                // (one lane per slot) until every tag matches.  A workgroup can be at
+                // (poll_slots) until every tag matches.  A workgroup can be at
                 // most one iteration ahead of another, so parity buffers plus the tag
                 // never confuse iterations t and t+2.
                 const int rel = t - J.t_begin;
