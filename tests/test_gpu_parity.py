@@ -488,3 +488,17 @@ def test_batch_of_eight_large_solves_shares_one_multi_launch():
     for r in range(8):
         _, o = oracle_solve(inst, tenure=15, iters=60, restart_seed=restart_seed(5, r))
         assert_same_result(o, res[r], f"eight-restart batch, restart {r}")
+
+
+@pytest.mark.parametrize("sched,groups", [(1, 0), (2, 0), (2, 5)])
+def test_relocates_across_many_routes(sched, groups):
+    """130 vehicles for 200 missions: relocates between routes more than 64
+    vehicles apart move more than one wavefront's worth of route offsets (and
+    many routes stay empty), on both LDS-resident schedules, Tabu and NS, equal
+    to the oracle."""
+    inst = make_instance(731, 160, 10, 130, 200)
+    dev = _dev(inst)
+    for variant in (0, 1):
+        _, o = oracle_solve(inst, variant=variant, tenure=11, iters=250)
+        g = at.solve(dev, variant=variant, tenure=11, iters=250, schedule=sched, n_groups=groups)
+        assert_same_result(o, g, f"130 vehicles schedule {sched} groups {groups} variant {variant}")
