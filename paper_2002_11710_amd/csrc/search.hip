@@ -195,7 +195,9 @@ __device__ __forceinline__ int route_of_pos(const int32_t *off, int V, int k)
 // ---------------------------------------------------------------------------
 // prep: per-position neighbours, per-gap ends, per-chunk ranks
 // ---------------------------------------------------------------------------
-template <typename TE>
+// GEND: also the per-gap route ends (gend), which only the segmented relocate
+// units read
+template <typename TE, bool GEND = true>
 __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nthr)
 {
     const int CH = c.chunk, M = c.M;
@@ -218,7 +220,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const bool first = i == 0 || rp != r;
         const bool last = i + 1 == M || rn != r;
         const bool last2 = i + 2 >= M || rn2 != r;   // for !last: position i + 1 closes the route
-        const int vr = c.vrow[r], vc = c.vcol[r], endr = c.off[r + 1];
+        const int vr = c.vrow[r], vc = c.vcol[r], endr = GEND ? c.off[r + 1] : 0;
         const int mc = c.mcol[m], mr = c.mrow[m];
         const int xp = c.mrow[mp], yn = c.mcol[mn], mrn = c.mrow[mn], yn2 = c.mcol[mn2];
         const int x = first ? vr : xp;
@@ -260,11 +262,11 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         c.posB[i] = make_int4(a + bb, l, (int)((uint32_t)m | ((uint32_t)r << 16)),
                               (int)((uint32_t)rank | ((uint32_t)(adj + kPackBias) << 6)));
         c.gap[i + r] = make_int4(x, mc, a, r);
-        c.gend[i + r] = (uint16_t)(endr + r + 1);
+        if (GEND) c.gend[i + r] = (uint16_t)(endr + r + 1);
         if (last) {
             // the gap after the route's last mission: from m's exit row to the base
             c.gap[i + 1 + r] = make_int4(mr, vc, bb, r);
-            c.gend[i + 1 + r] = (uint16_t)(endr + r + 1);
+            if (GEND) c.gend[i + 1 + r] = (uint16_t)(endr + r + 1);
         }
     }
     // the only gap of each empty route: on the highest threads, which have no
@@ -273,7 +275,7 @@ __device__ __forceinline__ void prep(const Ctx &c, const TE *tc, int tid, int nt
         const int e = c.off[r + 1], o = c.off[r], x = c.vrow[r], y = c.vcol[r];
         if (o == e) {
             c.gap[e + r] = make_int4(x, y, (int)tc[x + y], r);
-            c.gend[e + r] = (uint16_t)(e + r + 1);
+            if (GEND) c.gend[e + r] = (uint16_t)(e + r + 1);
         }
     }
 }
@@ -1149,8 +1151,14 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
     const UnitStart us0 = unit_start(c, gw);
     int t = J.t_begin;
     bool aborted = false;
+    // the thread that sets each move's tabu entries and writes the trace: lane 0 of
+    // the first wavefront with no position to prepare, when there is one
+    const int tx = (M + kWave - 1) / kWave * kWave < nthr ? (M + kWave - 1) / kWave * kWave : 0;
+    // the per-gap route ends serve the segmented relocate units only (the
+    // multi-workgroup schedule's units with 16-bit entries have no segments)
+    constexpr bool kGend = !(MULTI && sizeof(TE) == 2);
     if (t < J.t_end && !stopped) {
-        prep<TE>(c, tc, tid, nthr);
+        prep<TE, kGend>(c, tc, tid, nthr);
         bsync<WAVE>();
     }
     for (; t < J.t_end && !stopped; ++t) {
@@ -1164,7 +1172,6 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
         if (lane == 0) c.red[wave] = k;
         bsync<WAVE>();
         GMove mv{};
-        bool moved = false;   // wave 0: a move was decoded
         if (tid < kWave) {
             uint64_t w = lane < nwaves ? c.red[lane] : kKeyNone;
             w = wave_min(w);
@@ -1188,11 +1195,13 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                 xab = ab;
                 if (lane == 0) c.red[65] = ab;
             }
-            if (lane == 0) c.red[64] = w;
+            if (lane == 0) {
+                c.red[64] = w;
+                c.red[66] = 0;   // no move (kind 0) unless one is decoded below
+            }
             if (!xab && w != kKeyNone) {
                 // decode the move (uniform over the wave) and apply it
                 const uint32_t ix = (uint32_t)w;
-                moved = true;
                 if (!(ix >> 31)) {
                     const int m = (int)(ix >> 16);
                     const int G = (int)(ix & 0xFFFFu);
@@ -1211,6 +1220,12 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
                     mv.kind = 2;
                     mv.s1 = s1; mv.s2 = s2; mv.m1 = m1; mv.m2 = m2;
                     mv.v = r1; mv.rs = r2;            // the two vehicles
+                }
+                // the move for the thread that sets its tabu entries (below)
+                if (lane == 0) {
+                    c.red[66] = (uint64_t)mv.kind | ((uint64_t)(mv.kind == 1 ? mv.m : mv.m1) << 16) |
+                                ((uint64_t)mv.v << 32) | ((uint64_t)mv.rs << 48);
+                    c.red[67] = (uint64_t)mv.m2;
                 }
                 // apply it before the barrier that publishes the key (the neighbourhood
                 // search stops without applying a move that does not improve)
@@ -1243,22 +1258,27 @@ __device__ __forceinline__ void run_job(const JobDev &J, char *smem, int wg, int
             }
         }
         // the next iteration's records (they depend on the routes only)
-        if (t + 1 < J.t_end) prep<TE>(c, tc, tid, nthr);
-        if (tid == 0) {
-            // thread 0 (lane 0 of the wave that decoded the move) reads whether the move
-            // was tabu and makes the moved missions tabu for the vehicles they leave,
-            // behind its share of the records: nothing reads the tabu table before the
-            // next eval, after the barrier below
+        if (t + 1 < J.t_end) prep<TE, kGend>(c, tc, tid, nthr);
+        if (tid == tx) {
+            // one thread reads whether the move was tabu and makes the moved missions
+            // tabu for the vehicles they leave: nothing reads the tabu table before
+            // the next eval, after the barrier below.  It is a thread with no records
+            // to write when there is one, so its round trips stay off the barrier's path
             bool was_tabu = false;
-            if (use_tabu && moved) {
+            const uint64_t p0 = c.red[66];
+            const int kind = (int)(p0 & 0xFFFFu);
+            if (use_tabu && kind != 0) {
                 const int tval = t + J.tenure + 1;
-                if (mv.kind == 1) {
-                    was_tabu = (int)tabu[mv.v * M + mv.m] > t;
-                    tabu[mv.rs * M + mv.m] = (TB)tval;
+                const int m1 = (int)((p0 >> 16) & 0xFFFFu), v = (int)((p0 >> 32) & 0xFFFFu);
+                const int rs = (int)(p0 >> 48);
+                if (kind == 1) {
+                    was_tabu = (int)tabu[v * M + m1] > t;
+                    tabu[rs * M + m1] = (TB)tval;
                 } else {
-                    was_tabu = (int)tabu[mv.rs * M + mv.m1] > t || (int)tabu[mv.v * M + mv.m2] > t;
-                    tabu[mv.v * M + mv.m1] = (TB)tval;
-                    tabu[mv.rs * M + mv.m2] = (TB)tval;
+                    const int m2 = (int)(c.red[67] & 0xFFFFu);
+                    was_tabu = (int)tabu[rs * M + m1] > t || (int)tabu[v * M + m2] > t;
+                    tabu[v * M + m1] = (TB)tval;
+                    tabu[rs * M + m2] = (TB)tval;
                 }
             }
             if (writer && J.trace) {
